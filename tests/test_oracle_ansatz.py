@@ -1,0 +1,168 @@
+"""Pins of oracle.ansatz (CPU only).
+
+The paper prints no weights and no network outputs, so the forward is pinned
+by (i) the symmetries the paper designs in (translation invariance from the
+pooling, Hermiticity from the symmetrisation), (ii) a closed form of the
+symmetrisation, and (iii) independent library routines for each stage:
+torch's circular conv2d for the embedding and torch.nn.MultiheadAttention for
+the attention block.  A transposed operand, a wrong tap, a dropped residual
+or a wrong softmax scale fails one of these.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as Fnn
+
+from oracle import ansatz as oa
+
+ARCHS = {
+    "c1": oa.Arch(d=16, heads=2, layers=1, mlp=64),
+    "c2": oa.Arch(d=32, heads=4, layers=2, mlp=128),
+    "c3": oa.Arch(d=64, heads=4, layers=2, mlp=256),
+    "c4": oa.Arch(d=64, heads=8, layers=4, mlp=256),
+    "c5": oa.Arch(d=64, heads=4, layers=3, mlp=256),
+}
+
+
+def stress_params(arch, seed=0):
+    """Weights of O(1/sqrt(fan_in)) so that log rho varies by O(1) across configs."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, shape in oa.param_layout(arch):
+        fan_in = shape[0] * (shape[1] if name in ("conv1_w", "conv2_w") else 1) if len(shape) > 1 else 4
+        out.append(rng.standard_normal(int(np.prod(shape))) / math.sqrt(fan_in))
+    return np.concatenate(out)
+
+
+def rand_cfg(n, B, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 1 << n, size=(B, 2), dtype=np.uint64)
+
+
+def test_param_counts():
+    """P = 5 C1 + 2 C1 d + d + L (4 d^2 + 2 d m + m + d) + 2 d + 2 with C1 = d."""
+    expect = {"c1": 3794, "c2": 27202, "c3": 107650, "c4": 206594, "c5": 157122}
+    for k, a in ARCHS.items():
+        d, m, L, C1 = a.d, a.mlp, a.layers, a.C1
+        assert oa.num_params(a) == 5 * C1 + 2 * C1 * d + d + L * (4 * d * d + 2 * d * m + m + d) + 2 * d + 2
+        assert oa.num_params(a) == expect[k]
+
+
+def test_gelu_is_exact_erf_form():
+    u = torch.linspace(-6, 6, 1001, dtype=torch.float64)
+    assert torch.max(torch.abs(oa.gelu(u) - Fnn.gelu(u, approximate="none"))) < 1e-15
+
+
+@pytest.mark.parametrize("n", [4, 7, 16])
+def test_cyclic_shift_invariance(n):
+    """Mean pooling over sites makes log rho invariant under a simultaneous
+    cyclic shift of alpha and beta (App. B, global mean pooling)."""
+    arch = ARCHS["c3"]
+    th = stress_params(arch, 1)
+    cfg = rand_cfg(n, 64, 2)
+    mask = np.uint64((1 << n) - 1)
+    for sh in (1, 3):
+        rot = ((cfg << np.uint64(sh)) | (cfg >> np.uint64(n - sh))) & mask
+        a = oa.log_rho(th, arch, cfg, n)
+        b = oa.log_rho(th, arch, rot, n)
+        dz = a - b
+        assert torch.max(torch.abs(dz.real)) < 1e-12
+        assert torch.max(torch.abs(torch.remainder(dz.imag + math.pi, 2 * math.pi) - math.pi)) < 1e-12
+
+
+def test_hermiticity():
+    """Eq. log_sum_exp_conjugate makes rho(beta, alpha) = conj rho(alpha, beta)."""
+    arch = ARCHS["c2"]
+    n = 8
+    th = stress_params(arch, 3)
+    cfg = rand_cfg(n, 128, 4)
+    a = oa.log_rho(th, arch, cfg, n)
+    b = oa.log_rho(th, arch, cfg[:, ::-1].copy(), n)
+    assert torch.max(torch.abs(a.real - b.real)) < 1e-12
+    dz = a.imag + b.imag
+    assert torch.max(torch.abs(torch.remainder(dz + math.pi, 2 * math.pi) - math.pi)) < 1e-12
+
+
+def test_symmetrisation_closed_form():
+    """With head weights zero, z = b0 + i b1 for every configuration, so
+    log rho = log(2 Re e^z) = b0 + log 2 + log cos b1 (cos b1 > 0)."""
+    arch = ARCHS["c1"]
+    th = stress_params(arch, 5)
+    P = oa.num_params(arch)
+    th[P - 2 - 2 * arch.d:P - 2] = 0.0
+    th[P - 2:] = [0.3, 0.7]
+    cfg = rand_cfg(4, 32, 6)
+    lr = oa.log_rho(th, arch, cfg, 4)
+    assert torch.max(torch.abs(lr.real - (0.3 + math.log(2) + math.log(math.cos(0.7))))) < 1e-14
+    assert torch.max(torch.abs(lr.imag)) < 1e-14
+    th[P - 1] = 2.0   # cos < 0: principal branch gives Im = pi
+    lr = oa.log_rho(th, arch, cfg, 4)
+    assert torch.max(torch.abs(lr.real - (0.3 + math.log(2) + math.log(-math.cos(2.0))))) < 1e-14
+    assert torch.max(torch.abs(lr.imag - math.pi)) < 1e-14
+
+
+def test_embedding_against_torch_circular_conv2d():
+    """Eq. circ-conv read as a 2x1 kernel over (sites x dummy) with the (alpha,
+    beta) channels as input channels and circular padding after the last site."""
+    arch = ARCHS["c2"]
+    n, B = 8, 16
+    th = torch.as_tensor(stress_params(arch, 7))
+    p = oa.unflatten(th, arch)
+    a, b = oa.unpack_bits(rand_cfg(n, B, 8), n)
+    sa, sb = 1 - 2 * a, 1 - 2 * b
+    mine = oa.embed(p, sa, sb)
+    x = torch.stack([sa, sb], dim=1).unsqueeze(-1)                   # [B, 2, N, 1]
+    w1 = p["conv1_w"].permute(2, 1, 0).unsqueeze(-1)                 # [C1, 2, 2 taps, 1]
+    e = Fnn.gelu(Fnn.conv2d(Fnn.pad(x, (0, 0, 0, 1), mode="circular"), w1, p["conv1_b"]))
+    w2 = p["conv2_w"].permute(2, 1, 0).unsqueeze(-1)                 # [d, C1, 2, 1]
+    y = Fnn.gelu(Fnn.conv2d(Fnn.pad(e, (0, 0, 0, 1), mode="circular"), w2, p["conv2_b"]))
+    ref = y.squeeze(-1).transpose(1, 2)                              # [B, N, d]
+    assert torch.max(torch.abs(mine - ref)) < 1e-13
+
+
+def test_embedding_window_is_three_sites():
+    """Two width-2 convolutions see sites i, i+1, i+2: x_i is unchanged when
+    any other site flips."""
+    arch = ARCHS["c2"]
+    n = 8
+    th = torch.as_tensor(stress_params(arch, 9))
+    p = oa.unflatten(th, arch)
+    a, b = oa.unpack_bits(rand_cfg(n, 4, 10), n)
+    x0 = oa.embed(p, 1 - 2 * a, 1 - 2 * b)
+    for j in range(n):
+        a2 = a.clone()
+        a2[:, j] = 1 - a2[:, j]
+        x1 = oa.embed(p, 1 - 2 * a2, 1 - 2 * b)
+        changed = torch.any(torch.abs(x1 - x0) > 0, dim=(0, 2))
+        expect = torch.zeros(n, dtype=torch.bool)
+        for i in ((j - 2) % n, (j - 1) % n, j):
+            expect[i] = True
+        assert torch.equal(changed, expect), j
+
+
+@pytest.mark.parametrize("heads", [1, 4, 8])
+def test_attention_against_multihead_attention(heads):
+    """Eq. attn-head-appendix + X' residual against torch.nn.MultiheadAttention."""
+    d, n, B = 64, 12, 5
+    g = torch.Generator().manual_seed(heads)
+    x = torch.randn(B, n, d, dtype=torch.float64, generator=g)
+    wq, wk, wv, wo = (torch.randn(d, d, dtype=torch.float64, generator=g) / 8 for _ in range(4))
+    mine = oa.attention(x, wq, wk, wv, wo, heads)
+    mha = torch.nn.MultiheadAttention(d, heads, bias=False, batch_first=True, dtype=torch.float64)
+    with torch.no_grad():
+        mha.in_proj_weight.copy_(torch.cat([wq.T, wk.T, wv.T], dim=0))
+        mha.out_proj.weight.copy_(wo.T)
+        ref, _ = mha(x, x, x, need_weights=False)
+    assert torch.max(torch.abs(mine - (x + ref))) < 1e-12
+
+
+def test_layout_independent_of_n():
+    """The same parameter vector evaluates any chain length (App. B: pooling
+    removes the N dependence of the head)."""
+    arch = ARCHS["c5"]
+    th = stress_params(arch, 11)
+    for n in (3, 8, 40):
+        lr = oa.log_rho(th, arch, rand_cfg(n, 4, n), n)
+        assert torch.all(torch.isfinite(lr.real))
