@@ -12,15 +12,17 @@ Architecture (main text "Transformer density operator ansatz"; App. B):
 3. per layer: multi-head self-attention with W^Q, W^K, W^V split by head,
    softmax(Q K^T / sqrt(C2/h)) V, concatenation, W^O and a residual
    (Eq. attn-head-appendix and the X' equation); then a residual MLP
-   sub-layer x + act(x W1 + b1) W2 + b2 (the workloads give an MLP width; the
-   paper's single block omits it);
+   sub-layer x + max(0, x W1 + b1) W2 + b2 (the workloads give an MLP width;
+   the paper's block omits the feed-forward sub-layer, so it follows the
+   position-wise feed-forward network of the transformer the paper builds on,
+   Vaswani et al., with its ReLU);
 4. mean pooling over sites (Eq. global-pool-final), a dense head to two
    outputs [F0, F1], z = F0 + i F1;
 5. Hermitian symmetrisation log rho = log(exp z(alpha,beta) + conj exp z(beta,alpha))
    (Eq. log_sum_exp_conjugate).
 
 Readings where the paper is silent (listed with reasons in the design notes):
-activation = exact GELU u * Phi(u); conv taps (i, i+1 mod N) with channels
+convolution activation = exact GELU u * Phi(u); MLP activation = ReLU; conv taps (i, i+1 mod N) with channels
 (alpha, beta); C1 = C2 = d; no bias on the attention projections; attention
 scale 1/sqrt(d/h); principal branch of the complex log.
 
@@ -32,7 +34,7 @@ Pinned by invariants and independent re-derivations in
 tests/test_oracle_ansatz.py: cyclic-shift invariance, Hermiticity, closed form
 of the symmetrisation when the head weights vanish, the convolution against
 torch's own circular conv2d, the attention block against
-torch.nn.MultiheadAttention, and parameter-layout independence of N.
+torch.nn.MultiheadAttention, the MLP against torch.nn.Linear/ReLU, and parameter-layout independence of N.
 """
 from __future__ import annotations
 
@@ -125,13 +127,18 @@ def attention(x: torch.Tensor, wq, wk, wv, wo, heads: int) -> torch.Tensor:
     return x + cat @ wo
 
 
+def mlp(x: torch.Tensor, w1, b1, w2, b2) -> torch.Tensor:
+    """Position-wise feed-forward sub-layer max(0, x W1 + b1) W2 + b2 (no residual)."""
+    return torch.clamp(x @ w1 + b1, min=0.0) @ w2 + b2
+
+
 def z_out(theta: torch.Tensor, arch: Arch, bits_l: torch.Tensor, bits_r: torch.Tensor) -> torch.Tensor:
     """Complex network output z for the channel order (bits_l, bits_r)."""
     p = unflatten(theta, arch)
     x = embed(p, 1.0 - 2.0 * bits_l, 1.0 - 2.0 * bits_r)
     for l in range(arch.layers):
         x = attention(x, p[f"l{l}_wq"], p[f"l{l}_wk"], p[f"l{l}_wv"], p[f"l{l}_wo"], arch.heads)
-        x = x + gelu(x @ p[f"l{l}_w1"] + p[f"l{l}_b1"]) @ p[f"l{l}_w2"] + p[f"l{l}_b2"]
+        x = x + mlp(x, p[f"l{l}_w1"], p[f"l{l}_b1"], p[f"l{l}_w2"], p[f"l{l}_b2"])
     h = x.mean(dim=1)                                          # Eq. global-pool-final
     f = h @ p["head_w"] + p["head_b"]
     return torch.complex(f[:, 0], f[:, 1])

@@ -166,3 +166,18 @@ def test_layout_independent_of_n():
     for n in (3, 8, 40):
         lr = oa.log_rho(th, arch, rand_cfg(n, 4, n), n)
         assert torch.all(torch.isfinite(lr.real))
+
+
+def test_mlp_against_torch_linear_relu():
+    """The residual MLP sub-layer equals Linear -> ReLU -> Linear of torch.nn."""
+    d, m = 32, 128
+    g = torch.Generator().manual_seed(5)
+    x = torch.randn(7, 9, d, dtype=torch.float64, generator=g)
+    w1, w2 = torch.randn(d, m, dtype=torch.float64, generator=g), torch.randn(m, d, dtype=torch.float64, generator=g)
+    b1, b2 = torch.randn(m, dtype=torch.float64, generator=g), torch.randn(d, dtype=torch.float64, generator=g)
+    net = torch.nn.Sequential(torch.nn.Linear(d, m), torch.nn.ReLU(), torch.nn.Linear(m, d)).double()
+    with torch.no_grad():
+        net[0].weight.copy_(w1.T); net[0].bias.copy_(b1)
+        net[2].weight.copy_(w2.T); net[2].bias.copy_(b2)
+        ref = net(x)
+    assert torch.max(torch.abs(oa.mlp(x, w1, b1, w2, b2) - ref)) < 1e-12
