@@ -1,0 +1,162 @@
+/*
+ * tdo.h - C-ABI of the MI355X (gfx950) hot path of the transformer
+ * density-operator ansatz for steady states of dissipative spin chains
+ * (arXiv 2502.20723).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Configurations of the doubled space are packed as uint64_t[2] per entry:
+ *   word 0 = alpha, word 1 = beta (the row and column labels of
+ *   rho(alpha, beta) in the vectorisation |rho>> = sum rho_ab |a>|b>, App. A).
+ *   Bit i is site i; bit value 0 = spin up (sigma^z = +1), 1 = spin down.
+ *   Bits at positions >= n must be zero (TDO_EINVAL otherwise).
+ * - Complex numbers are two consecutive floats (re, im) or doubles.
+ * - Every pointer argument named as device memory must point to memory on the
+ *   context's device; host pointers are marked "host".  The caller owns and
+ *   allocates every input and output; the context owns its workspace.
+ * - Calls are asynchronous on the given stream (NULL = the legacy default
+ *   stream) unless stated otherwise; validation that needs only host data
+ *   happens before any launch, and on error no kernel has been launched.
+ * - Return value: TDO_OK (0) or a negative error code; the message of the
+ *   last error of the calling thread is returned by tdo_last_error().
+ *   Nothing aborts and no C++ exception crosses this interface.
+ */
+#ifndef TDO_H
+#define TDO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDO_OK 0
+#define TDO_EINVAL (-1)       /* invalid argument (shape, model, pointer) */
+#define TDO_ENOMEM (-2)       /* workspace budget too small or allocation failed */
+#define TDO_EHIP (-3)         /* a HIP runtime call failed */
+#define TDO_EUNSUPPORTED (-4) /* valid request outside what the library implements */
+
+/* Network shape.  d = width C2 of the site embeddings and attention
+ * (main text, "Transformer density operator ansatz"; App. B), heads = number
+ * of attention heads (d % heads == 0), layers = number of stacked
+ * [attention + MLP] blocks, mlp = hidden width of the residual MLP.
+ * Supported: d in {16, 32, 64}, d/heads in {8, 16}, mlp a multiple of 32 with
+ * mlp <= 512, 1 <= layers <= 16. */
+typedef struct {
+    int32_t d, heads, layers, mlp;
+} tdo_arch_t;
+
+/* Dissipative spin chain with periodic bonds and jumps sqrt(gamma) sigma^-_i.
+ * kind 0: Ising,  H = (V/4) sum sz_i sz_{i+1} + (g/2) sum sx_i  (Ising section)
+ * kind 1: XYZ,    H = sum_i sum_k J_k sk_i sk_{i+1} + B_k sk_i   (Heisenberg section)
+ * Fields Bx, By, Bz are used by kind 1 only; kind 0 ignores J*, B*. */
+typedef struct {
+    int32_t kind, n;
+    double V, g, Jx, Jy, Jz, Bx, By, Bz, gamma;
+} tdo_model_t;
+
+typedef enum { TDO_FP32 = 0, TDO_BF16 = 1 } tdo_prec_t;
+
+typedef struct tdo_ctx tdo_ctx_t;
+
+/* Create a context on HIP device `device` with at most `workspace_bytes` of
+ * device scratch (0 = a default of 8 GiB).  The workspace is allocated on
+ * first use and reused; calls that need more than the budget process their
+ * batch in chunks, and return TDO_ENOMEM only if a single chunk cannot fit. */
+int32_t tdo_ctx_create(tdo_ctx_t **ctx, int32_t device, size_t workspace_bytes);
+/* Synchronise the context's device and free everything it owns. */
+int32_t tdo_ctx_destroy(tdo_ctx_t *ctx);
+
+/* Number of real parameters of the ansatz (independent of n: the pooling of
+ * App. B removes the chain length from the parameter shapes).  Flat layout,
+ * row-major, x @ W convention, in this order:
+ *   conv1_w[2 taps][2 channels][d], conv1_b[d], conv2_w[2 taps][d][d], conv2_b[d],
+ *   per layer: Wq[d][d], Wk[d][d], Wv[d][d], Wo[d][d], W1[d][mlp], b1[mlp], W2[mlp][d], b2[d],
+ *   head_w[d][2], head_b[2].
+ * Tap 0 reads site i, tap 1 site i+1 (mod n); channel 0 = alpha, 1 = beta;
+ * spins enter as s = 1 - 2*bit.  Returns -1 for an invalid arch. */
+int64_t tdo_num_params(const tdo_arch_t *arch);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *tdo_last_error(void);
+
+/* Nonzero entries of rows x_b = cfg[b] of the vectorised Lindbladian
+ *   Lhat = -i(H (x) 1 - 1 (x) H^T) + sum_j gamma [L_j (x) L_j^* - 1/2 L_j^dag L_j (x) 1 - 1/2 1 (x) L_j^T L_j^*]
+ * (Eq. VecLin; App. A), for the model.  For each row, in this slot order,
+ * entries whose exact value is zero omitted:
+ *   diagonal; moves on alpha (Ising: flip site i; XYZ: flip bond (i,i+1));
+ *   moves on beta (same); XYZ with fields: single flips of alpha then beta;
+ *   dissipator moves (flip site i of alpha and beta, present iff both bits are 1).
+ * cfg: device uint64 [B][2]; conn: device uint64 [B][kmax][2]; mel: device
+ * float [B][kmax][2] (complex Lhat(x; y)); n_conn: device int32 [B].  Slots
+ * k >= n_conn[b] are not written.  kmax must be >= 3n+1 (5n+1 with fields).
+ * Requires 3 <= n <= 64. */
+int32_t tdo_connected(tdo_ctx_t *ctx, const tdo_model_t *model, const uint64_t *cfg, int64_t B,
+                      int32_t kmax, uint64_t *conn, float *mel, int32_t *n_conn, hipStream_t stream);
+
+/* Local Lindbladian estimator of App. C ("Optimization Procedure"):
+ *   L(x_b) = sum_{k < n_conn[b]} mel[b][k] * exp(log_rho_conn[b][k] - log_rho_x[b]),
+ * complex, in FP32.  A row with Re log_rho_x = -inf (rho(x) = 0) gives L = 0.
+ * log_rho_x: device float [B][2]; mel, log_rho_conn: device float [B][kmax][2];
+ * n_conn: device int32 [B]; lloc: device float [B][2]. */
+int32_t tdo_local_lindbladian(tdo_ctx_t *ctx, int64_t B, const float *log_rho_x, const float *mel,
+                              const int32_t *n_conn, int32_t kmax, const float *log_rho_conn,
+                              float *lloc, hipStream_t stream);
+
+/* log rho(alpha, beta) of the ansatz (Eq. log_sum_exp_conjugate on the network
+ * of App. B) for B configurations of an n-site chain, 3 <= n <= 64.
+ * params: device float [tdo_num_params]; cfg: device uint64 [B][2];
+ * log_rho: device float [B][2] (re, im; im on the principal branch (-pi, pi]).
+ * prec selects the GEMM precision (FP32 or BF16 operands, FP32 accumulation). */
+int32_t tdo_log_rho(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                    const uint64_t *cfg, int64_t B, tdo_prec_t prec, float *log_rho,
+                    hipStream_t stream);
+
+/* Vector-Jacobian product of log rho:
+ *   grad = sum_b seed[b][0] * d Re log rho(x_b)/d theta + seed[b][1] * d Im log rho(x_b)/d theta.
+ * seed: device float [B][2]; grad: device double [P], overwritten. */
+int32_t tdo_log_rho_vjp(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                        const uint64_t *cfg, int64_t B, tdo_prec_t prec, const float *seed,
+                        double *grad, hipStream_t stream);
+
+/* Cost and gradient at fixed samples (App. C, Eq. lossnetk):
+ *   loss = sum_b w_b |L(x_b)|^2 / sum_b w_b,
+ * with w_b = weights[b] (device double [B]) or 1 if weights is NULL.
+ * grad_mode 0 ("B"): gradient of the self-normalised estimator
+ *   F(theta) = sum r_b |L_b|^2 / sum r_b, r_b = w_b |rho_theta(x_b)|^2/|rho_theta0(x_b)|^2,
+ *   at theta0, i.e.  2 Re sum w conj(L_b) sum_k c_k e^{lr(y_k)-lr(x_b)} O(y_k) - 2 loss sum w Re O(x_b)
+ *   over sum w, O = d log rho/d theta; equal to d Cost/d theta when the
+ *   weights are the exact |rho|^2 of all configurations.
+ * grad_mode 1 ("A"): gradient of the weighted mean with w held fixed.
+ * loss: device double [1]; grad: device double [P]; lloc_out: device float
+ * [B][2] or NULL.  Reductions over samples are in FP64. */
+int32_t tdo_loss_grad(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params,
+                      const tdo_model_t *model, const uint64_t *cfg, int64_t B,
+                      const double *weights, tdo_prec_t prec, int32_t grad_mode, double *loss,
+                      double *grad, float *lloc_out, hipStream_t stream);
+
+/* Metropolis-Hastings on P ~ |rho|^2 (App. C, "Efficient Sampling Strategy"),
+ * `chains` independent chains, `sweeps` sweeps of 2n proposals each.  Proposal
+ * t of chain c draws Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (t mod 2^32, t >> 32, c, 0) and key (seed mod 2^32, seed >> 32), words r0..r2:
+ *   pair move iff r0 < floor(p_pair 2^32), flipping alpha_i and beta_i at
+ *   i = (r1 n) >> 32; otherwise flip bit j = (r1 2n) >> 32 of (alpha, beta);
+ *   accept iff (r2 + 0.5) 2^-32 < exp(2 Re(log rho' - log rho)).
+ * state: device uint64 [chains][2] in/out; state_log_rho: device float
+ * [chains][2] in/out (log rho of the states, as returned by tdo_log_rho);
+ * counter: host uint64, in/out, the proposal index t of the first proposal
+ * (advanced by sweeps*2n); samples: device uint64 [sweeps][chains][2], the state
+ * after each sweep.  0 <= p_pair <= 1. */
+int32_t tdo_sample(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                   int64_t chains, uint64_t *state, float *state_log_rho, uint64_t seed,
+                   uint64_t *counter, int32_t sweeps, float p_pair, tdo_prec_t prec,
+                   uint64_t *samples, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDO_H */

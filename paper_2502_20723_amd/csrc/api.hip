@@ -1,0 +1,249 @@
+// C-ABI entry points of libtdo (declared and documented in include/tdo.h):
+// argument validation, workspace planning and the launch sequences.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "lindblad.h"
+#include "netapi.h"
+#include "train.h"
+
+namespace tdo {
+
+static thread_local std::string g_err;
+
+int32_t set_error(int32_t code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+void clear_error() { g_err.clear(); }
+
+int32_t ensure_workspace(Context* c, size_t bytes) {
+  if (bytes <= c->ws_size) return TDO_OK;
+  TDO_CHECK(bytes <= c->budget, TDO_ENOMEM, "workspace of %zu bytes exceeds the context budget of %zu bytes",
+            bytes, c->budget);
+  TDO_HIP(hipSetDevice(c->device));
+  if (c->ws) {
+    TDO_HIP(hipDeviceSynchronize());
+    TDO_HIP(hipFree(c->ws));
+    c->ws = nullptr;
+    c->ws_size = 0;
+  }
+  // grow geometrically so that a sequence of growing requests allocates rarely
+  size_t want = std::min(c->budget, std::max(bytes, (size_t)(1.5 * (double)bytes)));
+  hipError_t e = hipMalloc(&c->ws, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    e = hipMalloc(&c->ws, bytes);
+    want = bytes;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c->ws = nullptr;
+    return set_error(TDO_ENOMEM, "hipMalloc of %zu workspace bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  c->ws_size = want;
+  return TDO_OK;
+}
+
+int32_t net_plan(const Context* c, const tdo_arch_t* arch, int n, bool bf16, NetPlan* np) {
+  TDO_TRY(make_pack_plan(arch, &np->pp));
+  TDO_CHECK(n >= 3 && n <= 64, TDO_EINVAL, "chain length n=%d outside [3, 64]", n);
+  np->bf16 = bf16;
+  np->n = n;
+  np->D = np->pp.D;
+  np->DH = arch->d / arch->heads;
+  np->span = n > 32;
+  np->cpb = np->span ? 1 : 32 / n;
+  np->masked = np->span ? (n < 64) : !(np->cpb == 1 && n == 32);
+  np->score_scale = (float)(1.4426950408889634 / std::sqrt((double)np->DH));
+  np->elem = bf16 ? 2 : 4;
+  np->num_cus = c->num_cus;
+  return TDO_OK;
+}
+
+int64_t blocks_for(const NetPlan& np, int64_t E) { return np.span ? 4 * E : 2 * ((E + np.cpb - 1) / np.cpb); }
+
+// Forward over E entries whose configurations are ecfg; z [E][2][2].
+int32_t run_forward(const NetPlan& np, const NetWeights& w, const uint64_t* ecfg, int64_t E, const int64_t* E_dev,
+                    float* xa, float* xb, const Saves* sv, float* z, hipStream_t st) {
+  const PackPlan& pp = np.pp;
+  const int L = pp.layers;
+  for (int l = 0; l < L; ++l) {
+    FwdArgs a{};
+    a.wpack = static_cast<const char*>(w.wpack) + (size_t)l * pp.layer_elems * np.elem;
+    a.b1 = w.b1 + (size_t)l * pp.M;
+    a.b2 = w.b2 + (size_t)l * pp.D;
+    a.table = w.table;
+    a.ecfg = ecfg;
+    a.n_entries_dev = E_dev;
+    a.n_entries = E;
+    a.x_in = (l % 2 == 0) ? xb : xa;  // layer l reads what layer l-1 wrote
+    a.x_out = (l % 2 == 0) ? xa : xb;
+    if (sv) {
+      a.save_x = static_cast<char*>(sv->x) + (size_t)l * sv->layer_bytes;
+      a.save_mid = static_cast<char*>(sv->mid) + (size_t)l * sv->layer_bytes;
+      a.save_last = sv->last;
+    }
+    a.head_w = w.head_w;
+    a.head_b = w.head_b;
+    a.z = z;
+    a.n = np.n;
+    a.cpb = np.cpb;
+    a.d_real = pp.d;
+    a.M = pp.M;
+    a.score_scale = np.score_scale;
+    a.first = l == 0;
+    a.last = l == L - 1;
+    a.masked = np.masked;
+    a.blocks_per_cu = 1;
+    TDO_TRY(launch_fwd_layer(a, np.bf16, np.D, np.DH, np.span, np.num_cus, st));
+  }
+  return TDO_OK;
+}
+
+int32_t pack_weights(const NetPlan& np, const float* params, NetWeights* w, hipStream_t st) {
+  TDO_TRY(launch_pack_forward(np.pp, params, np.bf16, w->wpack, w->b1, w->b2, st));
+  TDO_TRY(launch_embed_table(params, np.pp.d, np.D, w->table, st));
+  w->head_w = params + np.pp.off_head_w;
+  w->head_b = params + np.pp.off_head_b;
+  return TDO_OK;
+}
+
+void carve_weights(const NetPlan& np, Arena& ar, size_t* offs) {
+  const PackPlan& pp = np.pp;
+  offs[0] = ar.take<char>((size_t)pp.layer_elems * pp.layers * np.elem);
+  offs[1] = ar.take<float>((size_t)pp.layers * pp.M);
+  offs[2] = ar.take<float>((size_t)pp.layers * pp.D);
+  offs[3] = ar.take<float>(64 * (size_t)pp.D);
+}
+
+NetWeights weights_at(void* ws, const size_t* offs) {
+  NetWeights w{};
+  w.wpack = at<char>(ws, offs[0]);
+  w.b1 = at<float>(ws, offs[1]);
+  w.b2 = at<float>(ws, offs[2]);
+  w.table = at<float>(ws, offs[3]);
+  return w;
+}
+
+}  // namespace tdo
+
+using namespace tdo;
+
+extern "C" {
+
+const char* tdo_last_error(void) { return g_err.c_str(); }
+
+int32_t tdo_ctx_create(tdo_ctx_t** ctx, int32_t device, size_t workspace_bytes) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  int ndev = 0;
+  TDO_HIP(hipGetDeviceCount(&ndev));
+  TDO_CHECK(device >= 0 && device < ndev, TDO_EINVAL, "device %d not in [0, %d)", device, ndev);
+  TDO_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  TDO_HIP(hipGetDeviceProperties(&prop, device));
+  TDO_CHECK(std::strncmp(prop.gcnArchName, "gfx950", 6) == 0, TDO_EUNSUPPORTED,
+            "device %d is %s; this library is built for gfx950 (MI355X) only", device, prop.gcnArchName);
+  tdo_ctx_t* c = new (std::nothrow) tdo_ctx_t;
+  TDO_CHECK(c != nullptr, TDO_ENOMEM, "out of host memory");
+  c->c.device = device;
+  c->c.num_cus = prop.multiProcessorCount;
+  c->c.budget = workspace_bytes ? workspace_bytes : (size_t(8) << 30);
+  *ctx = c;
+  return TDO_OK;
+}
+
+int32_t tdo_ctx_destroy(tdo_ctx_t* ctx) {
+  clear_error();
+  if (!ctx) return TDO_OK;
+  if (ctx->c.ws) {
+    TDO_HIP(hipSetDevice(ctx->c.device));
+    TDO_HIP(hipDeviceSynchronize());
+    TDO_HIP(hipFree(ctx->c.ws));
+  }
+  delete ctx;
+  return TDO_OK;
+}
+
+int64_t tdo_num_params(const tdo_arch_t* arch) {
+  clear_error();
+  PackPlan pp;
+  if (make_pack_plan(arch, &pp) != TDO_OK) return -1;
+  return pp.nparams;
+}
+
+int32_t tdo_connected(tdo_ctx_t* ctx, const tdo_model_t* model, const uint64_t* cfg, int64_t B, int32_t kmax,
+                      uint64_t* conn, float* mel, int32_t* n_conn, hipStream_t stream) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  ModelDev m;
+  TDO_TRY(make_model(model, &m));
+  TDO_CHECK(B >= 0, TDO_EINVAL, "B=%lld < 0", (long long)B);
+  TDO_CHECK(kmax >= m.nslots, TDO_EINVAL, "kmax=%d smaller than the number of slots (%d) of a row", kmax,
+            m.nslots);
+  if (B == 0) return TDO_OK;
+  TDO_CHECK(cfg && conn && mel && n_conn, TDO_EINVAL, "NULL buffer");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  return launch_connected(m, cfg, B, kmax, conn, mel, n_conn, stream);
+}
+
+int32_t tdo_local_lindbladian(tdo_ctx_t* ctx, int64_t B, const float* log_rho_x, const float* mel,
+                              const int32_t* n_conn, int32_t kmax, const float* log_rho_conn, float* lloc,
+                              hipStream_t stream) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  TDO_CHECK(B >= 0 && kmax >= 1, TDO_EINVAL, "B=%lld, kmax=%d", (long long)B, kmax);
+  if (B == 0) return TDO_OK;
+  TDO_CHECK(log_rho_x && mel && n_conn && log_rho_conn && lloc, TDO_EINVAL, "NULL buffer");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  return launch_lloc_fixed(B, log_rho_x, mel, n_conn, kmax, log_rho_conn, lloc, stream);
+}
+
+int32_t tdo_log_rho(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params, int32_t n, const uint64_t* cfg,
+                    int64_t B, tdo_prec_t prec, float* log_rho, hipStream_t stream) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  TDO_CHECK(prec == TDO_FP32 || prec == TDO_BF16, TDO_EINVAL, "unknown precision %d", (int)prec);
+  NetPlan np;
+  TDO_TRY(net_plan(&ctx->c, arch, n, prec == TDO_BF16, &np));
+  TDO_CHECK(B >= 0, TDO_EINVAL, "B=%lld < 0", (long long)B);
+  if (B == 0) return TDO_OK;
+  TDO_CHECK(params && cfg && log_rho, TDO_EINVAL, "NULL buffer");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  Context& c = ctx->c;
+  Arena ar;
+  size_t woff[4];
+  carve_weights(np, ar, woff);
+  const size_t fixed = ar.used + 4096;
+  const size_t per_block = 32 * (size_t)np.D * 4;
+  TDO_CHECK(c.budget > fixed + 8 * per_block, TDO_ENOMEM, "workspace budget %zu too small", c.budget);
+  // entries per chunk: two FP32 residual buffers + z
+  const double per_entry = 2.0 * per_block * (np.span ? 4.0 : 2.0 / np.cpb) + 16.0;
+  int64_t chunk = (int64_t)((double)(c.budget - fixed) / per_entry);
+  chunk = std::min<int64_t>(chunk, B);
+  chunk = std::max<int64_t>(np.cpb, chunk / np.cpb * np.cpb);
+  const int64_t nblk = blocks_for(np, chunk);
+  const size_t oxa = ar.take<float>((size_t)nblk * 32 * np.D);
+  const size_t oxb = ar.take<float>((size_t)nblk * 32 * np.D);
+  const size_t oz = ar.take<float>((size_t)chunk * 4);
+  TDO_TRY(ensure_workspace(&c, ar.used));
+  NetWeights w = weights_at(c.ws, woff);
+  TDO_TRY(pack_weights(np, params, &w, stream));
+  for (int64_t e0 = 0; e0 < B; e0 += chunk) {
+    const int64_t E = std::min(chunk, B - e0);
+    TDO_TRY(run_forward(np, w, cfg + 2 * e0, E, nullptr, at<float>(c.ws, oxa), at<float>(c.ws, oxb), nullptr,
+                        at<float>(c.ws, oz), stream));
+    TDO_TRY(launch_symmetrise(nullptr, E, at<float>(c.ws, oz), log_rho + 2 * e0, stream));
+  }
+  return TDO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Shared definitions of the tdo HIP library: error state, context, workspace,
+// and small device helpers (wave reductions, packed configurations).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/tdo.h"
+
+namespace tdo {
+
+// ---------------------------------------------------------------- errors
+int32_t set_error(int32_t code, const char* fmt, ...);
+void clear_error();
+
+#define TDO_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::tdo::set_error(TDO_EHIP, "%s failed: %s (%s:%d)", #call,                \
+                              hipGetErrorString(e_), __FILE__, __LINE__);              \
+  } while (0)
+
+#define TDO_CHECK(cond, code, ...)                     \
+  do {                                                 \
+    if (!(cond)) return ::tdo::set_error(code, __VA_ARGS__); \
+  } while (0)
+
+#define TDO_TRY(expr)              \
+  do {                             \
+    int32_t s_ = (expr);           \
+    if (s_ != TDO_OK) return s_;   \
+  } while (0)
+
+// ---------------------------------------------------------------- context
+struct Context {
+  int device = 0;
+  int num_cus = 256;
+  size_t budget = 0;
+  void* ws = nullptr;
+  size_t ws_size = 0;
+};
+
+// Grow the context workspace to at least `bytes` (<= budget).
+int32_t ensure_workspace(Context* c, size_t bytes);
+
+// Bump allocator over a workspace region; all offsets aligned to 256 bytes.
+struct Arena {
+  size_t used = 0;
+  template <class T>
+  size_t take(size_t count) {
+    size_t off = used;
+    used = (used + count * sizeof(T) + 255) & ~size_t(255);
+    return off;
+  }
+};
+
+template <class T>
+inline T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+// ---------------------------------------------------------------- device helpers
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+__host__ __device__ inline uint64_t low_mask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
+// Cyclic shift by one site towards lower indices: bit i of the result is bit i+1 (mod n).
+__host__ __device__ inline uint64_t rot_down(uint64_t x, int n) {
+  return ((x >> 1) | (x << (n - 1))) & low_mask(n);
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace tdo
+
+struct tdo_ctx {
+  tdo::Context c;
+};

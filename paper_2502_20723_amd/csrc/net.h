@@ -1,0 +1,115 @@
+// Device building blocks of the transformer density operator on CDNA4 MFMA.
+//
+// Register layout.  A wave owns blocks of 32 sequence rows (sites of one or
+// more configurations).  Every activation lives in registers in the result
+// layout of the 32x32 MFMA: for a 32x32 tile (feature x row), lane l holds row
+// l%32 and the 16 features 8*(r/4) + 4*(l/32) + r%4, r = 0..15.  The same
+// registers, taken KPL at a time, are a valid A or B operand for a contraction
+// over those 32 features when the other operand enumerates features in the
+// same order; the packed weights below are laid out in exactly that order,
+// so GEMM chains (QKV, attention, W_O, MLP) never leave registers.
+// Computing the product as (row x feature) instead (swapping the A and B
+// operands) gives lane -> feature and r -> row, the layout used as operand of
+// contractions over rows (attention P.V and the weight gradients).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include "common.h"
+
+namespace tdo {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Feature (or row) index held by value r of lane half h in a 32x32 result tile.
+__host__ __device__ constexpr int tile_idx(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
+
+__device__ __forceinline__ short bf16_bits(float x) {
+  __bf16 b = (__bf16)x;
+  return __builtin_bit_cast(short, b);
+}
+
+// ------------------------------------------------------------------ precisions
+// BF16 operands, FP32 accumulation: v_mfma_f32_32x32x16_bf16 (8 values/lane).
+struct PBF16 {
+  static constexpr int KPL = 8;
+  static constexpr int STEPS = 32 / (2 * KPL);  // k-steps per 32-feature block
+  using elem_t = __bf16;                         // packed weight element
+  using op_t = bf16x8;
+  using save_t = __bf16;                         // saved activations for backward
+  __device__ static __forceinline__ f32x16 mma(op_t a, op_t b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ op_t op(const f32x16& v, int s) {
+    op_t o;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) o[t] = (__bf16)v[8 * s + t];
+    return o;
+  }
+  // Attention scores over DH features of head j (values [DH/2*j, DH/2*j + DH/2)).
+  template <int DH>
+  __device__ static __forceinline__ f32x16 scores(const f32x16& kv, const f32x16& qv, int j, f32x16 c) {
+    if constexpr (DH == 8) {
+      s16x4 a, b;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) { a[t] = bf16_bits(kv[4 * j + t]); b[t] = bf16_bits(qv[4 * j + t]); }
+      return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+    } else {
+      static_assert(DH == 16, "head width 8 or 16");
+      bf16x8 a, b;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) { a[t] = (__bf16)kv[8 * j + t]; b[t] = (__bf16)qv[8 * j + t]; }
+      return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+  }
+};
+
+// FP32 operands: v_mfma_f32_32x32x2f32 (1 value/lane).
+struct PF32 {
+  static constexpr int KPL = 1;
+  static constexpr int STEPS = 16;
+  using elem_t = float;
+  using op_t = float;
+  using save_t = float;
+  __device__ static __forceinline__ f32x16 mma(op_t a, op_t b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ op_t op(const f32x16& v, int s) { return v[s]; }
+  template <int DH>
+  __device__ static __forceinline__ f32x16 scores(const f32x16& kv, const f32x16& qv, int j, f32x16 c) {
+    constexpr int PER = DH / 2;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) c = __builtin_amdgcn_mfma_f32_32x32x2f32(kv[PER * j + t], qv[PER * j + t], c, 0, 0, 0);
+    return c;
+  }
+};
+
+// Packed weight fragment (out-block ob, in-block ib, k-step s) of a matrix
+// W[in][out] (x @ W convention): lane l holds W[32 ib + tile_idx(s*KPL+t, l/32)][32 ob + l%32]
+// for t < KPL; fragment f occupies elements [f*64*KPL, (f+1)*64*KPL).
+template <class P>
+__device__ __forceinline__ typename P::op_t ld_frag(const typename P::elem_t* base, int frag, int lane) {
+  if constexpr (P::KPL == 8) {
+    return *reinterpret_cast<const bf16x8*>(base + ((size_t)frag * 64 + lane) * 8);
+  } else {
+    return base[(size_t)frag * 64 + lane];
+  }
+}
+
+// Per-layer packed-weight offsets (elements), for width D and MLP width M.
+template <int D, int M>
+struct LayerPack {
+  static constexpr int NB = D / 32, MB = M / 32;
+  static constexpr int WQ = 0, WK = D * D, WV = 2 * D * D, WO = 3 * D * D;
+  static constexpr int W1 = 4 * D * D;        // [MB ob][NB ib][STEPS] fragments
+  static constexpr int W2 = 4 * D * D + D * M;  // [NB ob][MB ib][STEPS]
+  static constexpr int TOTAL = 4 * D * D + 2 * D * M;
+};
+
+// Exact ReLU of the feed-forward sub-layer.
+__device__ __forceinline__ float relu(float x) { return x > 0.f ? x : 0.f; }
+
+}  // namespace tdo

@@ -1,0 +1,418 @@
+// Forward pass of the transformer density operator (main text "Transformer
+// density operator ansatz"; App. B), one kernel launch per layer.
+//
+// Work decomposition.  The evaluation list holds E configurations, each
+// evaluated in two passes: the direct channel order (alpha, beta) giving
+// z(alpha, beta) and the swapped order (beta, alpha) giving z(beta, alpha)
+// (Eq. log_sum_exp_conjugate).  For n <= 32 a 32-row block holds
+// cpb = 32/n configurations of one pass (block g: pass g&1, configurations
+// (g>>1)*cpb ...); attention is masked to rows of the same configuration.  For
+// 32 < n <= 64 one configuration-pass spans two blocks (64 rows, rows >= n
+// masked).  A wave owns a tile of NBR blocks and keeps its rows in registers
+// through the whole layer: QKV projection, per-head softmax(QK^T/sqrt(dh))V,
+// W_O and residual, then the ReLU feed-forward sub-layer and residual.
+// The layer's packed weights are staged once per workgroup in LDS (BF16) or
+// read through the caches (FP32); workgroups are persistent over tiles.
+#include "common.h"
+#include "net.h"
+#include "netapi.h"
+
+namespace tdo {
+
+template <int D>
+struct EmbedRow {
+  // Window code of the two width-2 circular convolutions: x_i depends on
+  // sites i, i+1, i+2; code = t_i + 4 t_{i+1} + 16 t_{i+2},
+  // t = bit(channel 0) + 2 bit(channel 1).
+  __device__ static __forceinline__ int code(uint64_t c0, uint64_t c1, int i, int n) {
+    int cd = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int s = i + k;
+      s = s >= n ? s - n : s;
+      const int t = (int)((c0 >> s) & 1ull) + 2 * (int)((c1 >> s) & 1ull);
+      cd += t << (2 * k);
+    }
+    return cd;
+  }
+};
+
+// Table of the embedding: T[code][o] = act(b2 + e(t0,t1) W2[0] + e(t1,t2) W2[1]),
+// e(ta,tb) = act(b1 + s(ta) W1[0] + s(tb) W1[1]), act = exact GELU (Eq. circ-conv).
+__global__ void k_embed_table(const float* __restrict__ params, int d, int D, float* __restrict__ table) {
+  __shared__ float e0[64], e1[64];
+  const int code = blockIdx.x;
+  const int t0 = code & 3, t1 = (code >> 2) & 3, t2 = (code >> 4) & 3;
+  const float* w1 = params;            // [2 taps][2 ch][d]
+  const float* b1 = params + 4 * d;    // [d]
+  const float* w2 = b1 + d;            // [2 taps][d][d]
+  const float* b2 = w2 + 2 * d * d;    // [d]
+  auto spin = [](int t, int ch) { return 1.0f - 2.0f * (float)((t >> ch) & 1); };
+  auto gelu = [](float u) { return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f)); };
+  for (int c = threadIdx.x; c < d; c += blockDim.x) {
+    float a = b1[c] + spin(t0, 0) * w1[0 * d + c] + spin(t0, 1) * w1[1 * d + c] + spin(t1, 0) * w1[2 * d + c] +
+              spin(t1, 1) * w1[3 * d + c];
+    float b = b1[c] + spin(t1, 0) * w1[0 * d + c] + spin(t1, 1) * w1[1 * d + c] + spin(t2, 0) * w1[2 * d + c] +
+              spin(t2, 1) * w1[3 * d + c];
+    e0[c] = gelu(a);
+    e1[c] = gelu(b);
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < D; o += blockDim.x) {
+    float v = 0.f;
+    if (o < d) {
+      float acc = b2[o];
+      for (int c = 0; c < d; ++c) acc += e0[c] * w2[c * d + o] + e1[c] * w2[d * d + c * d + o];
+      v = gelu(acc);
+    }
+    table[code * D + o] = v;
+  }
+}
+
+template <class P, int D, int DH, bool SPAN>
+__global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
+  constexpr int NB = D / 32;            // feature blocks
+  constexpr int NBR = SPAN ? 2 : 1;     // row blocks per wave
+  constexpr int HPB = 32 / DH;          // heads per 32-feature block
+  constexpr int ST = P::STEPS;
+  using elem_t = typename P::elem_t;
+  using op_t = typename P::op_t;
+  using save_t = typename P::save_t;
+  constexpr bool WLDS = (P::KPL == 8);
+
+  extern __shared__ __align__(16) char smem[];
+  const int M = a.M, MB = M / 32;
+  const int wtotal = 4 * D * D + 2 * D * M;
+  // LDS carve-up: [weights (BF16 only)] [b1 M] [b2 D] [table 64*D] [pool scratch 4 waves * 64 float2]
+  elem_t* wl = reinterpret_cast<elem_t*>(smem);
+  float* b1s = reinterpret_cast<float*>(smem + (WLDS ? (size_t)wtotal * sizeof(elem_t) : 0));
+  float* b2s = b1s + M;
+  float* tabs = b2s + D;
+  float2* pools = reinterpret_cast<float2*>(tabs + (a.first ? 64 * D : 0));
+
+  // ---- stage weights, biases and the embedding table
+  const elem_t* wg = reinterpret_cast<const elem_t*>(a.wpack);
+  if constexpr (WLDS) {
+    const int n16 = wtotal * (int)sizeof(elem_t) / 16;
+    const int4* src = reinterpret_cast<const int4*>(wg);
+    int4* dst = reinterpret_cast<int4*>(wl);
+    for (int i = threadIdx.x; i < n16; i += blockDim.x) dst[i] = src[i];
+  }
+  for (int i = threadIdx.x; i < M; i += blockDim.x) b1s[i] = a.b1[i];
+  for (int i = threadIdx.x; i < D; i += blockDim.x) b2s[i] = a.b2[i];
+  if (a.first)
+    for (int i = threadIdx.x; i < 64 * D; i += blockDim.x) tabs[i] = a.table[i];
+  __syncthreads();
+  const elem_t* W = WLDS ? wl : wg;
+  constexpr int FR = ST * 64 * P::KPL;  // elements per (ob, ib) fragment group
+  const elem_t* Wq = W + 0 * D * D;
+  const elem_t* Wk = W + 1 * D * D;
+  const elem_t* Wv = W + 2 * D * D;
+  const elem_t* Wo = W + 3 * D * D;
+  const elem_t* W1 = W + 4 * D * D;
+  const elem_t* W2 = W + 4 * D * D + D * M;
+
+  const int lane = threadIdx.x & 63, h = lane >> 5, lr = lane & 31;
+  const int wave = threadIdx.x >> 6;
+  const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
+  const int n = a.n, cpb = a.cpb;
+  const int64_t ntiles = SPAN ? 2 * E : 2 * ((E + cpb - 1) / cpb);
+  const float sc = a.score_scale;  // log2(e)/sqrt(dh)
+
+  for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+    const int pass = (int)(tile & 1);
+    // first entry of the tile and the slot/validity of this lane's rows
+    const int64_t e0 = SPAN ? (tile >> 1) : (tile >> 1) * cpb;
+    int rslot[NBR];
+    bool rvalid[NBR];
+#pragma unroll
+    for (int rb = 0; rb < NBR; ++rb) {
+      const int row = rb * 32 + lr;
+      if (SPAN) { rslot[rb] = 0; rvalid[rb] = row < n; }
+      else { rslot[rb] = lr / n; rvalid[rb] = (lr / n) < cpb && (e0 + lr / n) < E; }
+    }
+
+    // ---- residual stream x (feature x row), FP32
+    f32x16 x[NBR][NB];
+    const int64_t gblk0 = tile * NBR;
+    if (a.first) {
+#pragma unroll
+      for (int rb = 0; rb < NBR; ++rb) {
+        const int row = rb * 32 + lr;
+        int code = 0;
+        if (rvalid[rb]) {
+          const int64_t e = e0 + rslot[rb];
+          const uint64_t al = a.ecfg[2 * e], be = a.ecfg[2 * e + 1];
+          const uint64_t c0 = pass ? be : al, c1 = pass ? al : be;
+          code = EmbedRow<D>::code(c0, c1, SPAN ? row : (lr % n), n);
+        }
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) {
+          const float* tr = tabs + code * D + 32 * ob;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 v = *reinterpret_cast<const float4*>(tr + 8 * q + 4 * h);
+            x[rb][ob][4 * q + 0] = v.x; x[rb][ob][4 * q + 1] = v.y;
+            x[rb][ob][4 * q + 2] = v.z; x[rb][ob][4 * q + 3] = v.w;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int rb = 0; rb < NBR; ++rb)
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) {
+          const float4* src = reinterpret_cast<const float4*>(a.x_in + (((gblk0 + rb) * NB + ob) * 64 + lane) * 16);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 v = src[q];
+            x[rb][ob][4 * q + 0] = v.x; x[rb][ob][4 * q + 1] = v.y;
+            x[rb][ob][4 * q + 2] = v.z; x[rb][ob][4 * q + 3] = v.w;
+          }
+        }
+    }
+    auto save = [&](void* dst, const f32x16 (&v)[NBR][NB]) {
+      save_t* s = reinterpret_cast<save_t*>(dst);
+#pragma unroll
+      for (int rb = 0; rb < NBR; ++rb)
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) {
+          save_t* p = s + (((gblk0 + rb) * NB + ob) * 64 + lane) * 16;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) p[r] = (save_t)v[rb][ob][r];
+        }
+    };
+    if (a.save_x) save(a.save_x, x);
+
+    // ---- attention: operands of x taken before the residual is updated
+    op_t xo[NBR][NB][ST];
+#pragma unroll
+    for (int rb = 0; rb < NBR; ++rb)
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int s = 0; s < ST; ++s) xo[rb][ib][s] = P::op(x[rb][ib], s);
+
+#pragma unroll 1
+    for (int hb = 0; hb < NB; ++hb) {
+      f32x16 q[NBR], k[NBR], v[NBR];
+#pragma unroll
+      for (int rb = 0; rb < NBR; ++rb) {
+        q[rb] = f32x16{};
+        k[rb] = f32x16{};
+        v[rb] = f32x16{};
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+          for (int s = 0; s < ST; ++s) {
+            const int f = (hb * NB + ib) * ST + s;
+            q[rb] = P::mma(ld_frag<P>(Wq, f, lane), xo[rb][ib][s], q[rb]);
+            k[rb] = P::mma(ld_frag<P>(Wk, f, lane), xo[rb][ib][s], k[rb]);
+            v[rb] = P::mma(xo[rb][ib][s], ld_frag<P>(Wv, f, lane), v[rb]);  // (row x feature)
+          }
+      }
+      f32x16 o[NBR];
+      float invl[NBR][HPB];
+#pragma unroll
+      for (int rb = 0; rb < NBR; ++rb) o[rb] = f32x16{};
+#pragma unroll
+      for (int j = 0; j < HPB; ++j) {
+        // V fragments restricted to head j (A operand: lane -> feature lr)
+        const bool mine = (lr / DH) == j;
+#pragma unroll
+        for (int qb = 0; qb < NBR; ++qb) {
+          f32x16 st[NBR];
+          float m = -INFINITY;
+#pragma unroll
+          for (int kb = 0; kb < NBR; ++kb) {
+            st[kb] = P::template scores<DH>(k[kb], q[qb], j, f32x16{});
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int key = kb * 32 + tile_idx(r, h);
+              bool ok;
+              if (SPAN) ok = key < n;
+              else ok = a.masked ? ((key / n) == rslot[qb] && (key / n) < cpb) : true;
+              const float s2 = ok ? st[kb][r] * sc : -INFINITY;
+              st[kb][r] = s2;
+              m = fmaxf(m, s2);
+            }
+          }
+          m = fmaxf(m, __shfl_xor(m, 32, 64));
+          float l = 0.f;
+#pragma unroll
+          for (int kb = 0; kb < NBR; ++kb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const float p = (m == -INFINITY) ? 0.f : exp2f(st[kb][r] - m);
+              st[kb][r] = p;
+              l += p;
+            }
+          l += __shfl_xor(l, 32, 64);
+          invl[qb][j] = l > 0.f ? 1.0f / l : 0.f;
+#pragma unroll
+          for (int kb = 0; kb < NBR; ++kb)
+#pragma unroll
+            for (int s = 0; s < ST; ++s) {
+              const op_t vv = P::op(v[kb], s);
+              const op_t va = mine ? vv : op_t{};
+              o[qb] = P::mma(va, P::op(st[kb], s), o[qb]);
+            }
+        }
+      }
+      // normalise per head, then W_O into the residual
+#pragma unroll
+      for (int qb = 0; qb < NBR; ++qb) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) o[qb][r] *= invl[qb][DH == 8 ? r / 4 : r / 8];  // value r holds a feature of head r*4/DH
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+          for (int s = 0; s < ST; ++s)
+            x[qb][ob] = P::mma(ld_frag<P>(Wo, (ob * NB + hb) * ST + s, lane), P::op(o[qb], s), x[qb][ob]);
+      }
+    }
+    if (a.save_mid) save(a.save_mid, x);
+
+    // ---- feed-forward sub-layer: x += relu(x W1 + b1) W2 + b2
+#pragma unroll
+    for (int rb = 0; rb < NBR; ++rb)
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int s = 0; s < ST; ++s) xo[rb][ib][s] = P::op(x[rb][ib], s);
+#pragma unroll 1
+    for (int c = 0; c < MB; ++c) {
+      float bias[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bias[r] = b1s[32 * c + tile_idx(r, h)];
+#pragma unroll
+      for (int rb = 0; rb < NBR; ++rb) {
+        f32x16 u = f32x16{};
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+          for (int s = 0; s < ST; ++s) u = P::mma(ld_frag<P>(W1, (c * NB + ib) * ST + s, lane), xo[rb][ib][s], u);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) u[r] = relu(u[r] + bias[r]);
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+          for (int s = 0; s < ST; ++s)
+            x[rb][ob] = P::mma(ld_frag<P>(W2, (ob * MB + c) * ST + s, lane), P::op(u, s), x[rb][ob]);
+      }
+    }
+#pragma unroll
+    for (int rb = 0; rb < NBR; ++rb)
+#pragma unroll
+      for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[rb][ob][r] += b2s[32 * ob + tile_idx(r, h)];
+
+    if (!a.last) {
+#pragma unroll
+      for (int rb = 0; rb < NBR; ++rb)
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) {
+          float4* dst = reinterpret_cast<float4*>(a.x_out + (((gblk0 + rb) * NB + ob) * 64 + lane) * 16);
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq)
+            dst[qq] = make_float4(x[rb][ob][4 * qq], x[rb][ob][4 * qq + 1], x[rb][ob][4 * qq + 2], x[rb][ob][4 * qq + 3]);
+        }
+      continue;
+    }
+    // ---- last layer: save x_L, mean pooling over sites, dense head to z (Eq. global-pool-final)
+    if (a.save_last) save(a.save_last, x);
+    float2* pw = pools + wave * 64;
+#pragma unroll
+    for (int rb = 0; rb < NBR; ++rb) {
+      float f0 = 0.f, f1 = 0.f;
+#pragma unroll
+      for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int f = 32 * ob + tile_idx(r, h);
+          if (f < a.d_real) {
+            f0 += x[rb][ob][r] * a.head_w[2 * f];
+            f1 += x[rb][ob][r] * a.head_w[2 * f + 1];
+          }
+        }
+      f0 += __shfl_xor(f0, 32, 64);
+      f1 += __shfl_xor(f1, 32, 64);
+      if (h == 0) pw[rb * 32 + lr] = make_float2(f0, f1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nslot = SPAN ? 1 : cpb;
+    if (lane < nslot) {
+      const int64_t e = e0 + lane;
+      if (e < E) {
+        float s0 = 0.f, s1 = 0.f;
+        const int base = SPAN ? 0 : lane * n;
+        for (int i = 0; i < n; ++i) { s0 += pw[base + i].x; s1 += pw[base + i].y; }
+        const float inv = 1.0f / (float)n;
+        a.z[(e * 2 + pass) * 2 + 0] = s0 * inv + a.head_b[0];
+        a.z[(e * 2 + pass) * 2 + 1] = s1 * inv + a.head_b[1];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// log rho = log(e^{z1} + conj(e^{z2})) on the principal branch (Eq. log_sum_exp_conjugate).
+__global__ void k_symmetrise(const int64_t* __restrict__ E_dev, int64_t E_host, const float* __restrict__ z,
+                             float* __restrict__ lr) {
+  const int64_t E = E_dev ? *E_dev : E_host;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+    const float a0 = z[4 * e], a1 = z[4 * e + 1];   // z(alpha, beta)
+    const float b0 = z[4 * e + 2], b1 = z[4 * e + 3];  // z(beta, alpha), conjugated below
+    const float mx = fmaxf(a0, b0);
+    const float ea = expf(a0 - mx), eb = expf(b0 - mx);
+    float sa, ca, sb, cb;
+    sincosf(a1, &sa, &ca);
+    sincosf(b1, &sb, &cb);
+    const float sr = ea * ca + eb * cb, si = ea * sa - eb * sb;
+    lr[2 * e] = mx + 0.5f * logf(sr * sr + si * si);
+    lr[2 * e + 1] = atan2f(si, sr);
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+template <class P, int D, int DH, bool SPAN>
+static int32_t launch_layer_t(const FwdArgs& a, int num_cus, hipStream_t st) {
+  const size_t wbytes = (P::KPL == 8) ? (size_t)(4 * D * D + 2 * D * a.M) * sizeof(typename P::elem_t) : 0;
+  const size_t lds = wbytes + (size_t)(a.M + D) * 4 + (a.first ? 64 * D * 4 : 0) + 4 * 64 * sizeof(float2);
+  auto kern = k_fwd_layer<P, D, DH, SPAN>;
+  TDO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int blocks = num_cus * a.blocks_per_cu;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
+  TDO_HIP(hipGetLastError());
+  return TDO_OK;
+}
+
+template <class P>
+static int32_t launch_layer_p(const FwdArgs& a, int D, int DH, bool span, int num_cus, hipStream_t st) {
+  if (D == 32 && DH == 8) return span ? launch_layer_t<P, 32, 8, true>(a, num_cus, st) : launch_layer_t<P, 32, 8, false>(a, num_cus, st);
+  if (D == 64 && DH == 8) return span ? launch_layer_t<P, 64, 8, true>(a, num_cus, st) : launch_layer_t<P, 64, 8, false>(a, num_cus, st);
+  if (D == 64 && DH == 16) return span ? launch_layer_t<P, 64, 16, true>(a, num_cus, st) : launch_layer_t<P, 64, 16, false>(a, num_cus, st);
+  return set_error(TDO_EUNSUPPORTED, "no forward kernel for padded width %d, head width %d", D, DH);
+}
+
+int32_t launch_fwd_layer(const FwdArgs& a, bool bf16, int D, int DH, bool span, int num_cus, hipStream_t st) {
+  return bf16 ? launch_layer_p<PBF16>(a, D, DH, span, num_cus, st) : launch_layer_p<PF32>(a, D, DH, span, num_cus, st);
+}
+
+int32_t launch_embed_table(const float* params, int d, int D, float* table, hipStream_t st) {
+  hipLaunchKernelGGL(k_embed_table, dim3(64), dim3(64), 0, st, params, d, D, table);
+  TDO_HIP(hipGetLastError());
+  return TDO_OK;
+}
+
+int32_t launch_symmetrise(const int64_t* E_dev, int64_t E_host, const float* z, float* lr, hipStream_t st) {
+  hipLaunchKernelGGL(k_symmetrise, dim3(1024), dim3(256), 0, st, E_dev, E_host, z, lr);
+  TDO_HIP(hipGetLastError());
+  return TDO_OK;
+}
+
+}  // namespace tdo

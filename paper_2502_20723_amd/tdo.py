@@ -1,0 +1,248 @@
+"""Thin ctypes binding of libtdo (C-ABI in include/tdo.h).
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step of the computation runs in the library's kernels.
+Loading fails loudly if the built library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdo.so")
+
+TDO_FP32, TDO_BF16 = 0, 1
+PREC = {"fp32": TDO_FP32, "bf16": TDO_BF16}
+
+# The entry points declared in include/tdo.h.
+EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_error", "tdo_connected",
+           "tdo_local_lindbladian", "tdo_log_rho", "tdo_log_rho_vjp", "tdo_loss_grad", "tdo_sample")
+
+
+class ArchT(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("heads", ctypes.c_int32), ("layers", ctypes.c_int32), ("mlp", ctypes.c_int32)]
+
+
+class ModelT(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32)] + [
+        (k, ctypes.c_double) for k in ("V", "g", "Jx", "Jy", "Jz", "Bx", "By", "Bz", "gamma")]
+
+
+class TdoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tdo error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               f"(paper_2502_20723_amd/csrc/build.sh)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.tdo_last_error.restype = ctypes.c_char_p
+        L.tdo_num_params.restype = i64
+        L.tdo_num_params.argtypes = [ctypes.POINTER(ArchT)]
+        L.tdo_ctx_create.argtypes = [ctypes.POINTER(vp), i32, sz]
+        L.tdo_ctx_destroy.argtypes = [vp]
+        L.tdo_connected.argtypes = [vp, ctypes.POINTER(ModelT), vp, i64, i32, vp, vp, vp, vp]
+        L.tdo_local_lindbladian.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp]
+        L.tdo_log_rho.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp]
+        L.tdo_log_rho_vjp.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp, vp]
+        L.tdo_loss_grad.argtypes = [vp, ctypes.POINTER(ArchT), vp, ctypes.POINTER(ModelT), vp, i64, vp, i32, i32,
+                                    vp, vp, vp, vp]
+        L.tdo_sample.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, i64, vp, vp, ctypes.c_uint64,
+                                 ctypes.POINTER(ctypes.c_uint64), i32, ctypes.c_float, i32, vp, vp]
+        for name in EXPORTS:
+            if name not in ("tdo_last_error", "tdo_num_params", "tdo_ctx_create", "tdo_ctx_destroy"):
+                getattr(L, name).restype = i32
+        L.tdo_ctx_create.restype = i32
+        L.tdo_ctx_destroy.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise TdoError(code, lib().tdo_last_error().decode())
+
+
+def arch_t(a: dict) -> ArchT:
+    return ArchT(int(a["d"]), int(a["heads"]), int(a["layers"]), int(a["mlp"]))
+
+
+def model_t(m: dict) -> ModelT:
+    return ModelT(int(m["kind"]), int(m["n"]), *[float(m.get(k, 0.0) or 0.0) for k in
+                                                 ("V", "g", "Jx", "Jy", "Jz", "Bx", "By", "Bz")],
+                  float(m.get("gamma", 1.0)))
+
+
+def num_params(a: dict) -> int:
+    p = lib().tdo_num_params(ctypes.byref(arch_t(a)))
+    if p < 0:
+        raise TdoError(-1, lib().tdo_last_error().decode())
+    return int(p)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA {dtype} tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+@dataclass
+class Ctx:
+    """A library context on one device with a workspace budget."""
+
+    device: int = 0
+    workspace_bytes: int = 0
+
+    def __post_init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().tdo_ctx_create(ctypes.byref(h), self.device, self.workspace_bytes))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().tdo_ctx_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ entry points
+    def connected(self, model: dict, cfg: torch.Tensor, kmax: int | None = None):
+        n = int(model["n"])
+        if kmax is None:
+            fields = model.get("kind") == 1 and (model.get("Bx", 0) or model.get("By", 0))
+            kmax = (5 if fields else 3) * n + 1
+        B = cfg.shape[0]
+        _dev(cfg, torch.uint64, (B, 2), "cfg")
+        conn = torch.zeros((B, kmax, 2), dtype=torch.uint64, device=cfg.device)
+        mel = torch.zeros((B, kmax, 2), dtype=torch.float32, device=cfg.device)
+        ncon = torch.zeros((B,), dtype=torch.int32, device=cfg.device)
+        _check(lib().tdo_connected(self.h, ctypes.byref(model_t(model)), _ptr(cfg), B, kmax, _ptr(conn), _ptr(mel),
+                                   _ptr(ncon), _stream()))
+        return conn, mel, ncon
+
+    def local_lindbladian(self, lr_x, mel, ncon, lr_conn):
+        B, kmax = mel.shape[0], mel.shape[1]
+        _dev(lr_x, torch.float32, (B, 2), "log_rho_x")
+        _dev(mel, torch.float32, (B, kmax, 2), "mel")
+        _dev(ncon, torch.int32, (B,), "n_conn")
+        _dev(lr_conn, torch.float32, (B, kmax, 2), "log_rho_conn")
+        out = torch.empty((B, 2), dtype=torch.float32, device=mel.device)
+        _check(lib().tdo_local_lindbladian(self.h, B, _ptr(lr_x), _ptr(mel), _ptr(ncon), kmax, _ptr(lr_conn),
+                                           _ptr(out), _stream()))
+        return out
+
+    def log_rho(self, arch: dict, params, n: int, cfg, prec="fp32"):
+        B = cfg.shape[0]
+        _dev(params, torch.float32, (num_params(arch),), "params")
+        _dev(cfg, torch.uint64, (B, 2), "cfg")
+        out = torch.empty((B, 2), dtype=torch.float32, device=cfg.device)
+        _check(lib().tdo_log_rho(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(cfg), B, PREC[prec],
+                                 _ptr(out), _stream()))
+        return out
+
+    def log_rho_vjp(self, arch: dict, params, n: int, cfg, seed, prec="fp32"):
+        B = cfg.shape[0]
+        _dev(params, torch.float32, (num_params(arch),), "params")
+        _dev(cfg, torch.uint64, (B, 2), "cfg")
+        _dev(seed, torch.float32, (B, 2), "seed")
+        grad = torch.empty((num_params(arch),), dtype=torch.float64, device=cfg.device)
+        _check(lib().tdo_log_rho_vjp(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(cfg), B, PREC[prec],
+                                     _ptr(seed), _ptr(grad), _stream()))
+        return grad
+
+    def loss_grad(self, arch: dict, params, model: dict, cfg, weights=None, prec="fp32", mode="B",
+                  want_lloc=False):
+        B = cfg.shape[0]
+        P = num_params(arch)
+        _dev(params, torch.float32, (P,), "params")
+        _dev(cfg, torch.uint64, (B, 2), "cfg")
+        if weights is not None:
+            _dev(weights, torch.float64, (B,), "weights")
+        loss = torch.empty((1,), dtype=torch.float64, device=cfg.device)
+        grad = torch.empty((P,), dtype=torch.float64, device=cfg.device)
+        lloc = torch.empty((B, 2), dtype=torch.float32, device=cfg.device) if want_lloc else None
+        _check(lib().tdo_loss_grad(self.h, ctypes.byref(arch_t(arch)), _ptr(params), ctypes.byref(model_t(model)),
+                                   _ptr(cfg), B, _ptr(weights), PREC[prec], {"B": 0, "A": 1}[mode], _ptr(loss),
+                                   _ptr(grad), _ptr(lloc), _stream()))
+        return loss, grad, lloc
+
+    def sample(self, arch: dict, params, n: int, state, state_lr, seed: int, counter: int, sweeps: int,
+               p_pair=0.5, prec="fp32"):
+        C = state.shape[0]
+        _dev(params, torch.float32, (num_params(arch),), "params")
+        _dev(state, torch.uint64, (C, 2), "state")
+        _dev(state_lr, torch.float32, (C, 2), "state_log_rho")
+        samples = torch.empty((sweeps, C, 2), dtype=torch.uint64, device=state.device)
+        ctr = ctypes.c_uint64(counter)
+        _check(lib().tdo_sample(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, C, _ptr(state), _ptr(state_lr),
+                                seed, ctypes.byref(ctr), sweeps, p_pair, PREC[prec], _ptr(samples), _stream()))
+        return samples, int(ctr.value)
+
+
+_default_ctx = None
+
+
+def default_ctx() -> Ctx:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Ctx(torch.cuda.current_device())
+    return _default_ctx
+
+
+class LogRho(torch.autograd.Function):
+    """log rho (complex as [B, 2] float) with the library's backward as VJP."""
+
+    @staticmethod
+    def forward(ctx, params, arch, n, cfg, prec):
+        ctx.save_for_backward(params, cfg)
+        ctx.arch, ctx.n, ctx.prec = arch, n, prec
+        return default_ctx().log_rho(arch, params, n, cfg, prec)
+
+    @staticmethod
+    def backward(ctx, g):
+        params, cfg = ctx.saved_tensors
+        grad = default_ctx().log_rho_vjp(ctx.arch, params, ctx.n, cfg, g.contiguous().float(), ctx.prec)
+        return grad.to(params.dtype), None, None, None, None
+
+
+class LossGrad(torch.autograd.Function):
+    """Cost of the samples; its backward returns the library's gradient
+    estimator (mode B by default) times the upstream scalar."""
+
+    @staticmethod
+    def forward(ctx, params, arch, model, cfg, weights, prec, mode):
+        loss, grad, _ = default_ctx().loss_grad(arch, params, model, cfg, weights, prec, mode)
+        ctx.save_for_backward(grad)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return (g.double() * grad).to(torch.float32), None, None, None, None, None, None
