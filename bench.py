@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Throughput of the loss-gradient step of the transformer density operator
+on one MI355X, BF16-MFMA path against the plain FP32 path.
+
+One step = one call of tdo_loss_grad (gradient estimator of mode B) on the
+dissipative Ising chain N = 32 (V = 2, g drawn from U[0.5, 2], gamma = 1),
+transformer d = 64, 8 heads, 4 layers, MLP 256, B = 65536 samples: the
+Lindbladian rows of every sample, the forward pass over every connected
+configuration (two passes each), L_loc, the FP64 loss reduction, the backward
+pass of every layer and the FP64 gradient reduction.  Inputs are synthetic
+(seeded parameters at the N(0, 0.02) initialisation and i.i.d. uniform
+configurations) and resident in HBM before the timed region.
+
+Printed: one JSON line on stdout.  value = configurations per second of the
+BF16 path, where a configuration is one evaluated log rho (a sample or one of
+its nonzero Lindbladian row entries), each costing two transformer passes.
+Progress goes to stderr.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "configs/sec fwd+bwd (loss grad), BF16-MFMA vs FP32 GPU at matched loss error"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}  # MI355X dense MFMA
+KERNELS = ("fwd_layer", "bwd_mlp", "bwd_attn")
+# Source files whose change invalidates a recorded HBM-traffic measurement.
+KERNEL_SOURCES = {
+    "fwd_layer": ("net_fwd.hip", "net.h", "netapi.h"),
+    "bwd_mlp": ("net_bwd.hip", "net.h", "netapi.h"),
+    "bwd_attn": ("net_bwd.hip", "net.h", "netapi.h"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_flops_per_unit(kernel, n, d, m):
+    """Algorithmic FLOPs of one configuration-pass through one layer.
+
+    forward: QKV 6nd^2, W_O 2nd^2, scores and P.V 4n^2 d, MLP 4ndm;
+    backward of the MLP: input gradient 4ndm + weight gradients 4ndm;
+    backward of attention: input and weight gradients of QKV and W_O 16nd^2,
+    dP, dV, dQ, dK 8n^2 d.  Recomputation is not counted."""
+    if kernel == "fwd_layer":
+        return 8 * n * d * d + 4 * n * n * d + 4 * n * d * m
+    if kernel == "bwd_mlp":
+        return 8 * n * d * m
+    if kernel == "bwd_attn":
+        return 16 * n * d * d + 8 * n * n * d
+    raise ValueError(kernel)
+
+
+def sources_digest(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2502_20723_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, or None when
+    there is none or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256") != sources_digest(kernel):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precs", default="fp32,bf16")
+    ap.add_argument("--workspace-gib", type=float, default=48.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the loss check against the oracle")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one elementwise copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the samples shard "
+              f"across GPUs with one all-reduce of the gradient, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2502_20723_amd import synth, tdo
+
+    name = "ising_n32"
+    wl = synth.workload(name)
+    arch, model, B = wl["arch"], wl["model"], wl["B"]
+    n, d, m, L = model["n"], arch["d"], arch["mlp"], arch["layers"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    params_np = synth.params(arch, wl["seed"], "init")
+    cfg_np = synth.configs(n, B, 3000)
+    params = torch.from_numpy(params_np).to(dev)
+    cfg = torch.from_numpy(cfg_np).to(dev)
+    ctx = tdo.Ctx(0, int(args.workspace_gib * (1 << 30)))
+    log(f"bench: {name} n={n} B={B} arch={arch} g={model['g']:.6f} P={tdo.num_params(arch)}")
+
+    # configurations evaluated per step: every sample plus its nonzero off-diagonal row entries
+    conn, _, ncon = ctx.connected(model, cfg)
+    diag_present = (conn[:, 0, 0] == cfg[:, 0]) & (conn[:, 0, 1] == cfg[:, 1])
+    E_step = int(ncon.sum().item()) + int((~diag_present).sum().item())
+    del conn
+    units_step = 2 * (E_step + B)  # config-passes per layer per step (mode B adds one pass over the samples)
+    log(f"bench: {E_step} configurations per step (K_avg {E_step / B:.2f})")
+
+    if args.copy_calibration_mib:
+        nel = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(nel, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {args.copy_calibration_mib} MiB done")
+        del src, dst
+
+    results = {}
+    stream = torch.cuda.current_stream()
+    for prec in [p for p in args.precs.split(",") if p]:
+        for i in range(args.warmup):
+            t0 = time.time()
+            loss, grad, _ = ctx.loss_grad(arch, params, model, cfg, None, prec, "B")
+            torch.cuda.synchronize()
+            log(f"bench: {prec} warmup step {i} {time.time() - t0:.2f} s loss {float(loss[0]):.6e}")
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for i in range(args.steps):
+            loss, grad, _ = ctx.loss_grad(arch, params, model, cfg, None, prec, "B")
+            if i == 0 or i == args.steps - 1:
+                log(f"bench: {prec} step {i} queued")
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        total_ms = ev0.elapsed_time(ev1)
+        kt = {k: ctx.profile_read(k) for k in KERNELS}
+        ctx.profile(False)
+        ms = total_ms / args.steps
+        r = dict(ms_per_step=ms, configs_per_s=E_step / (ms / 1e3), loss=float(loss[0]),
+                 grad_norm=float(torch.linalg.vector_norm(grad).item()), kernels={})
+        for k, (kms, cnt) in kt.items():
+            fl = kernel_flops_per_unit(k, n, d, m) * units_step * L * args.steps
+            r["kernels"][k] = dict(total_ms=kms, launches=cnt, avg_launch_ms=kms / max(cnt, 1),
+                                   share=kms / total_ms, tflops=fl / (kms / 1e3) / 1e12 if kms > 0 else 0.0,
+                                   flops_per_launch=fl / max(cnt, 1))
+        results[prec] = r
+        log(f"bench: {prec} {ms:.1f} ms/step, {r['configs_per_s'] / 1e6:.3f} M configs/s; kernels " +
+            ", ".join(f"{k} {v['share'] * 100:.0f}% {v['tflops']:.0f} TF/s" for k, v in r["kernels"].items()))
+
+    main_prec = "bf16" if "bf16" in results else next(iter(results))
+    R = results[main_prec]
+    dom = max(R["kernels"], key=lambda k: R["kernels"][k]["total_ms"])
+    kd = R["kernels"][dom]
+    achieved = kd["tflops"]
+    roofline = dict(bound="mfma", kernel=dom, achieved=achieved, peak=PEAK_TFLOPS[main_prec], unit="TFLOP/s",
+                    frac=achieved / PEAK_TFLOPS[main_prec], traffic=recorded_traffic(dom, name),
+                    avg_launch_ms=kd["avg_launch_ms"], flops_per_launch=kd["flops_per_launch"],
+                    flops_per_unit=kernel_flops_per_unit(dom, n, d, m),
+                    unit_def="one configuration-pass through one layer")
+
+    # matched loss error: the loss on sampled rows of the same batch, against the FP64 oracle
+    loss_err = None
+    if not args.no_check:
+        from oracle import ansatz as oa
+        from oracle import lindblad as ol
+        from oracle import vmc
+        pick = np.sort(np.random.default_rng(7).choice(B, 16, replace=False))
+        w = torch.zeros(B, dtype=torch.float64, device=dev)
+        w[torch.from_numpy(pick).to(dev)] = 1.0
+        F_ref, _, _ = vmc.loss(params_np.astype(np.float64), oa.Arch(**arch), ol.Model(**model), cfg_np[pick])
+        loss_err = {}
+        for prec in results:
+            lg, _, _ = ctx.loss_grad(arch, params, model, cfg, w, prec, "B")
+            loss_err[prec] = abs(float(lg[0]) - F_ref) / abs(F_ref)
+        log(f"bench: loss rel. error vs FP64 oracle on 16 sampled rows: {loss_err}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(arch, model, params_np, cfg_np)
+
+    out = {
+        "metric": METRIC,
+        "value": R["configs_per_s"],
+        "unit": "configs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": R["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_prec,
+        "data": "synthetic",
+        "config": {"workload": f"{name}: dissipative Ising chain n=32 V=2 g={model['g']:.4f} gamma=1, "
+                               f"d=64 heads=8 layers=4 mlp=256, B=65536, gradient mode B",
+                   "B": B, "n": n, "configs_per_step": E_step, "parallelism": "single GPU"},
+        "fp32_value": results.get("fp32", {}).get("configs_per_s"),
+        "speedup_bf16_over_fp32": (results["bf16"]["configs_per_s"] / results["fp32"]["configs_per_s"]
+                                   if "bf16" in results and "fp32" in results else None),
+        "loss_rel_err_vs_oracle": loss_err,
+        "per_precision": results,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(arch, model, params_np, cfg_np):
+    """The FP64 oracle's loss and gradient (mode B) on a bounded prefix of the
+    same samples, timed on the host; scaled to configurations per second."""
+    import numpy as np
+    import torch
+
+    from oracle import ansatz as oa
+    from oracle import lindblad as ol
+    from oracle import vmc
+
+    A, M = oa.Arch(**arch), ol.Model(**model)
+    th = params_np.astype(np.float64)
+
+    def run(S):
+        rows = ol.connected(M, cfg_np[:S])
+        E = sum(1 + sum(1 for y in r[0] if not (y[0] == c[0] and y[1] == c[1])) for r, c in zip(rows, cfg_np[:S]))
+        t0 = time.time()
+        vmc.loss_grad(th, A, M, cfg_np[:S], None, mode="B")
+        return E, time.time() - t0
+
+    E, t = run(2)
+    S = int(min(max(2, round(2 * 15.0 / max(t, 1e-3))), 512))
+    E, t = run(S)
+    log(f"bench: oracle {S} samples ({E} configurations) in {t:.1f} s")
+    return {"value": E / t, "unit": "configs/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"first {S} of the 65536 samples ({E} configurations), FP64 loss and gradient (mode B)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -83,6 +83,19 @@ int64_t tdo_num_params(const tdo_arch_t *arch);
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *tdo_last_error(void);
 
+/* Per-kernel timing of the context's launches (measurement support, not part
+ * of the method).  tdo_profile(ctx, 1) discards earlier records and starts
+ * bracketing every launch of the kernel groups "fwd_layer" (one transformer
+ * layer of the forward pass), "bwd_mlp" and "bwd_attn" (the backward of the
+ * feed-forward and attention sub-layers) with HIP events recorded on the
+ * launch stream; tdo_profile(ctx, 0) stops recording and discards the records.
+ * tdo_profile_read waits for the recorded events of the named group and
+ * returns the summed launch durations in milliseconds and the launch count
+ * (both 0 if none).  Events are pooled by the context: no device memory is
+ * allocated. */
+int32_t tdo_profile(tdo_ctx_t *ctx, int32_t enable);
+int32_t tdo_profile_read(tdo_ctx_t *ctx, const char *kernel, double *total_ms, int64_t *launches);
+
 /* Nonzero entries of rows x_b = cfg[b] of the vectorised Lindbladian
  *   Lhat = -i(H (x) 1 - 1 (x) H^T) + sum_j gamma [L_j (x) L_j^* - 1/2 L_j^dag L_j (x) 1 - 1/2 1 (x) L_j^T L_j^*]
  * (Eq. VecLin; App. A), for the model.  For each row, in this slot order,

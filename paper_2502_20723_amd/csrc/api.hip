@@ -24,6 +24,53 @@ int32_t set_error(int32_t code, const char* fmt, ...) {
 }
 void clear_error() { g_err.clear(); }
 
+// ---------------------------------------------------------------- profiler
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void Profiler::recycle() {
+  for (auto& r : recs) {
+    pool.push_back(r.start);
+    pool.push_back(r.stop);
+  }
+  recs.clear();
+}
+
+void Profiler::destroy() {
+  recycle();
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+}
+
+ProfScope::ProfScope(Profiler* p_, const char* name_, hipStream_t st_) : p(p_), name(name_), st(st_) {
+  if (p && p->enabled) {
+    start = p->get();
+    if (start) (void)hipEventRecord(start, st);
+  }
+}
+
+ProfScope::~ProfScope() {
+  if (!start) return;
+  hipEvent_t stop = p->get();
+  if (!stop) {
+    p->pool.push_back(start);
+    return;
+  }
+  (void)hipEventRecord(stop, st);
+  p->recs.push_back({name, start, stop});
+}
+
 int32_t ensure_workspace(Context* c, size_t bytes) {
   if (bytes <= c->ws_size) return TDO_OK;
   TDO_CHECK(bytes <= c->budget, TDO_ENOMEM, "workspace of %zu bytes exceeds the context budget of %zu bytes",
@@ -65,6 +112,7 @@ int32_t net_plan(const Context* c, const tdo_arch_t* arch, int n, bool bf16, Net
   np->score_scale = (float)(1.4426950408889634 / std::sqrt((double)np->DH));
   np->elem = bf16 ? 2 : 4;
   np->num_cus = c->num_cus;
+  np->prof = const_cast<Profiler*>(&c->prof);
   return TDO_OK;
 }
 
@@ -103,6 +151,7 @@ int32_t run_forward(const NetPlan& np, const NetWeights& w, const uint64_t* ecfg
     a.last = l == L - 1;
     a.masked = np.masked;
     a.blocks_per_cu = 1;
+    ProfScope ps(np.prof, "fwd_layer", st);
     TDO_TRY(launch_fwd_layer(a, np.bf16, np.D, np.DH, np.span, np.num_cus, st));
   }
   return TDO_OK;
@@ -164,12 +213,40 @@ int32_t tdo_ctx_create(tdo_ctx_t** ctx, int32_t device, size_t workspace_bytes) 
 int32_t tdo_ctx_destroy(tdo_ctx_t* ctx) {
   clear_error();
   if (!ctx) return TDO_OK;
-  if (ctx->c.ws) {
-    TDO_HIP(hipSetDevice(ctx->c.device));
-    TDO_HIP(hipDeviceSynchronize());
-    TDO_HIP(hipFree(ctx->c.ws));
-  }
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  TDO_HIP(hipDeviceSynchronize());
+  ctx->c.prof.destroy();
+  if (ctx->c.ws) TDO_HIP(hipFree(ctx->c.ws));
   delete ctx;
+  return TDO_OK;
+}
+
+int32_t tdo_profile(tdo_ctx_t* ctx, int32_t enable) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  for (auto& r : ctx->c.prof.recs) TDO_HIP(hipEventSynchronize(r.stop));
+  ctx->c.prof.recycle();
+  ctx->c.prof.enabled = enable != 0;
+  return TDO_OK;
+}
+
+int32_t tdo_profile_read(tdo_ctx_t* ctx, const char* kernel, double* total_ms, int64_t* launches) {
+  clear_error();
+  TDO_CHECK(ctx && kernel && total_ms && launches, TDO_EINVAL, "NULL argument");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  double t = 0.0;
+  int64_t k = 0;
+  for (auto& r : ctx->c.prof.recs) {
+    if (std::strcmp(r.name, kernel) != 0) continue;
+    TDO_HIP(hipEventSynchronize(r.stop));
+    float ms = 0.f;
+    TDO_HIP(hipEventElapsedTime(&ms, r.start, r.stop));
+    t += ms;
+    ++k;
+  }
+  *total_ms = t;
+  *launches = k;
   return TDO_OK;
 }
 

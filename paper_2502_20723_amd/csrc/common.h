@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/tdo.h"
 
@@ -36,6 +37,32 @@ void clear_error();
     if (s_ != TDO_OK) return s_;   \
   } while (0)
 
+// ---------------------------------------------------------------- profiling
+// Optional per-kernel timing: when enabled, each launch of a named kernel
+// group is bracketed by HIP events recorded on the launch stream.  Events come
+// from a pool owned by the context and are read (and returned) on request.
+struct Profiler {
+  bool enabled = false;
+  struct Rec {
+    const char* name;
+    hipEvent_t start, stop;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  void recycle();
+  void destroy();
+};
+
+struct ProfScope {
+  Profiler* p;
+  const char* name;
+  hipStream_t st;
+  hipEvent_t start = nullptr;
+  ProfScope(Profiler* p_, const char* name_, hipStream_t st_);
+  ~ProfScope();
+};
+
 // ---------------------------------------------------------------- context
 struct Context {
   int device = 0;
@@ -43,6 +70,7 @@ struct Context {
   size_t budget = 0;
   void* ws = nullptr;
   size_t ws_size = 0;
+  Profiler prof;
 };
 
 // Grow the context workspace to at least `bytes` (<= budget).

@@ -33,9 +33,12 @@ int32_t make_pack_plan(const tdo_arch_t* arch, PackPlan* pp) {
   return TDO_OK;
 }
 
+// Fragments of the layer matrices (bwd = false): Wq, Wk, Wv, Wo [D][D], W1 [D][M],
+// W2 [M][D]; or of their transposes (bwd = true), used by the backward pass:
+// Wq^T, Wk^T, Wv^T, Wo^T [D][D], W2^T [D][M], W1^T [M][D].
 template <int KPL, class T>
-__global__ void k_pack_forward(const float* __restrict__ params, PackPlan pp, T* __restrict__ out,
-                               float* __restrict__ b1o, float* __restrict__ b2o) {
+__global__ void k_pack(const float* __restrict__ params, PackPlan pp, bool bwd, T* __restrict__ out,
+                       float* __restrict__ b1o, float* __restrict__ b2o) {
   constexpr int ST = 32 / (2 * KPL);
   const int D = pp.D, M = pp.M, d = pp.d;
   const int64_t total = pp.layer_elems * pp.layers;
@@ -43,21 +46,23 @@ __global__ void k_pack_forward(const float* __restrict__ params, PackPlan pp, T*
     const int l = (int)(e / pp.layer_elems);
     int64_t k = e % pp.layer_elems;
     const float* lp = params + pp.off_layer0 + l * pp.layer_stride;
+    // Packed matrix A[in][out], in < in_p (padded).  Forward: A = W, W[rows][cols]
+    // row-major with rows = in, cols = out.  Backward: A = W^T, A[in][out] = W[out][in].
     const float* src;
-    int in_p, in_r, out_r;
+    int in_p, wrows, wcols;
     if (k < 4LL * D * D) {
       const int mt = (int)(k / ((int64_t)D * D));
       k -= (int64_t)mt * D * D;
       src = lp + (int64_t)mt * d * d;
-      in_p = D; in_r = d; out_r = d;
+      in_p = D; wrows = d; wcols = d;
     } else if (k < 4LL * D * D + (int64_t)D * M) {
       k -= 4LL * D * D;
-      src = lp + 4LL * d * d;
-      in_p = D; in_r = d; out_r = M;
+      if (!bwd) { src = lp + 4LL * d * d; in_p = D; wrows = d; wcols = M; }                      // W1 [d][M]
+      else { src = lp + 4LL * d * d + (int64_t)d * M + M; in_p = D; wrows = M; wcols = d; }      // W2^T, W2 [M][d]
     } else {
       k -= 4LL * D * D + (int64_t)D * M;
-      src = lp + 4LL * d * d + (int64_t)d * M + M;
-      in_p = M; in_r = M; out_r = d;
+      if (!bwd) { src = lp + 4LL * d * d + (int64_t)d * M + M; in_p = M; wrows = M; wcols = d; } // W2 [M][d]
+      else { src = lp + 4LL * d * d; in_p = M; wrows = d; wcols = M; }                           // W1^T, W1 [d][M]
     }
     const int frag = (int)(k / (64 * KPL));
     const int rem = (int)(k % (64 * KPL));
@@ -67,9 +72,15 @@ __global__ void k_pack_forward(const float* __restrict__ params, PackPlan pp, T*
     const int ob = frag / (ST * (in_p / 32));
     const int in = 32 * ib + tile_idx(s * KPL + t, lane >> 5);
     const int o = 32 * ob + (lane & 31);
-    const float v = (in < in_r && o < out_r) ? src[(int64_t)in * out_r + o] : 0.0f;
+    float v = 0.0f;
+    if (!bwd) {
+      if (in < wrows && o < wcols) v = src[(int64_t)in * wcols + o];
+    } else {
+      if (o < wrows && in < wcols) v = src[(int64_t)o * wcols + in];
+    }
     out[e] = (T)v;
   }
+  if (bwd) return;
   // biases (padded): b1 [L][M], b2 [L][D]
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)pp.layers * (M + D);
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -84,18 +95,25 @@ __global__ void k_pack_forward(const float* __restrict__ params, PackPlan pp, T*
   }
 }
 
-int32_t launch_pack_forward(const PackPlan& pp, const float* params, bool bf16, void* wpack, float* b1,
-                            float* b2, hipStream_t st) {
+static int32_t launch_pack(const PackPlan& pp, const float* params, bool bf16, bool bwd, void* wpack, float* b1,
+                           float* b2, hipStream_t st) {
   const int64_t total = pp.layer_elems * pp.layers;
   const int blocks = (int)std::min<int64_t>(ceil_div(total, 256), 4096);
   if (bf16)
-    hipLaunchKernelGGL((k_pack_forward<8, __bf16>), dim3(blocks), dim3(256), 0, st, params, pp,
-                       (__bf16*)wpack, b1, b2);
+    hipLaunchKernelGGL((k_pack<8, __bf16>), dim3(blocks), dim3(256), 0, st, params, pp, bwd, (__bf16*)wpack, b1, b2);
   else
-    hipLaunchKernelGGL((k_pack_forward<1, float>), dim3(blocks), dim3(256), 0, st, params, pp, (float*)wpack,
-                       b1, b2);
+    hipLaunchKernelGGL((k_pack<1, float>), dim3(blocks), dim3(256), 0, st, params, pp, bwd, (float*)wpack, b1, b2);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
+}
+
+int32_t launch_pack_forward(const PackPlan& pp, const float* params, bool bf16, void* wpack, float* b1,
+                            float* b2, hipStream_t st) {
+  return launch_pack(pp, params, bf16, false, wpack, b1, b2, st);
+}
+
+int32_t launch_pack_backward(const PackPlan& pp, const float* params, bool bf16, void* wpack, hipStream_t st) {
+  return launch_pack(pp, params, bf16, true, wpack, nullptr, nullptr, st);
 }
 
 }  // namespace tdo

@@ -42,5 +42,40 @@ int32_t make_pack_plan(const tdo_arch_t* arch, PackPlan* pp);
 // biases b1 [L][M], b2 [L][D].
 int32_t launch_pack_forward(const PackPlan& pp, const float* params, bool bf16, void* wpack, float* b1,
                             float* b2, hipStream_t st);
+// L layers of transposed fragments: Wq^T, Wk^T, Wv^T, Wo^T [D][D], then W2^T [D][M], W1^T [M][D].
+int32_t launch_pack_backward(const PackPlan& pp, const float* params, bool bf16, void* wpack, hipStream_t st);
+
+}  // namespace tdo
+
+namespace tdo {
+
+struct BwdArgs {
+  const void* wf;               // this layer's forward fragments
+  const void* wb;               // this layer's transposed fragments
+  const float* b1;              // [M]
+  const void* save_x;           // layer input
+  const void* save_mid;         // feed-forward input
+  const float* g_in;            // incoming gradient [blocks][D/32][64][16] (NULL: from seeds)
+  const float* seeds;           // last layer: per configuration-pass (dF0, dF1), [E][2][2]
+  const float* head_w;          // [d][2]
+  float* g_out;                 // outgoing gradient
+  float* partial;               // per-workgroup FP32 weight-gradient accumulators
+  const int64_t* n_entries_dev;
+  int64_t n_entries;
+  int n, cpb, span, masked, d_real, M;
+  float score_scale, inv_sqrt_dh;
+};
+
+size_t bwd_mlp_lds(int D, int M);
+int32_t launch_bwd_mlp(const BwdArgs& a, bool bf16, int D, int blocks, hipStream_t st);
+int32_t launch_bwd_attn(const BwdArgs& a, bool bf16, int D, int DH, int blocks, hipStream_t st);
+int32_t launch_bwd_head(bool bf16, int D, const void* save_last, const float* seeds, const int64_t* E_dev,
+                        int64_t E_host, int n, int cpb, int span, int d_real, double* gw, double* gb, hipStream_t st);
+int32_t launch_embed_scatter(int D, const float* dx0, const uint64_t* ecfg, const int64_t* E_dev, int64_t E_host,
+                             int n, int cpb, int span, float* partial, int blocks, hipStream_t st);
+int32_t launch_embed_params(const float* params, const double* dT, int d, int D, double* grad, hipStream_t st);
+int32_t launch_reduce_partials(const float* part, int nparts, int64_t len, double* out, hipStream_t st);
+int32_t launch_scatter_layer(const double* mlp, const double* attn, int d, int D, int M, double scale, double* g,
+                             hipStream_t st);
 
 }  // namespace tdo

@@ -2,14 +2,6 @@
 #include "common.h"
 
 extern "C" {
-int32_t tdo_log_rho_vjp(tdo_ctx_t*, const tdo_arch_t*, const float*, int32_t, const uint64_t*, int64_t, tdo_prec_t,
-                        const float*, double*, hipStream_t) {
-  return tdo::set_error(TDO_EUNSUPPORTED, "tdo_log_rho_vjp: not implemented yet");
-}
-int32_t tdo_loss_grad(tdo_ctx_t*, const tdo_arch_t*, const float*, const tdo_model_t*, const uint64_t*, int64_t,
-                      const double*, tdo_prec_t, int32_t, double*, double*, float*, hipStream_t) {
-  return tdo::set_error(TDO_EUNSUPPORTED, "tdo_loss_grad: not implemented yet");
-}
 int32_t tdo_sample(tdo_ctx_t*, const tdo_arch_t*, const float*, int32_t, int64_t, uint64_t*, float*, uint64_t,
                    uint64_t*, int32_t, float, tdo_prec_t, uint64_t*, hipStream_t) {
   return tdo::set_error(TDO_EUNSUPPORTED, "tdo_sample: not implemented yet");

@@ -1,6 +1,8 @@
 // Host-side plans shared by the forward, backward and sampling drivers.
 #pragma once
 
+#include <cmath>
+
 #include "common.h"
 #include "netapi.h"
 
@@ -11,6 +13,7 @@ struct NetPlan {
   bool bf16, span, masked;
   int D, DH, n, cpb, elem, num_cus;
   float score_scale;
+  Profiler* prof;
 };
 
 struct NetWeights {

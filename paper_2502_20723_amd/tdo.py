@@ -19,8 +19,9 @@ TDO_FP32, TDO_BF16 = 0, 1
 PREC = {"fp32": TDO_FP32, "bf16": TDO_BF16}
 
 # The entry points declared in include/tdo.h.
-EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_error", "tdo_connected",
-           "tdo_local_lindbladian", "tdo_log_rho", "tdo_log_rho_vjp", "tdo_loss_grad", "tdo_sample")
+EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_error", "tdo_profile",
+           "tdo_profile_read", "tdo_connected", "tdo_local_lindbladian", "tdo_log_rho", "tdo_log_rho_vjp",
+           "tdo_loss_grad", "tdo_sample")
 
 
 class ArchT(ctypes.Structure):
@@ -54,6 +55,8 @@ def lib() -> ctypes.CDLL:
         L.tdo_num_params.argtypes = [ctypes.POINTER(ArchT)]
         L.tdo_ctx_create.argtypes = [ctypes.POINTER(vp), i32, sz]
         L.tdo_ctx_destroy.argtypes = [vp]
+        L.tdo_profile.argtypes = [vp, i32]
+        L.tdo_profile_read.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.tdo_connected.argtypes = [vp, ctypes.POINTER(ModelT), vp, i64, i32, vp, vp, vp, vp]
         L.tdo_local_lindbladian.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp]
         L.tdo_log_rho.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp]
@@ -131,6 +134,16 @@ class Ctx:
             self.close()
         except Exception:
             pass
+
+    # ------------------------------------------------------------ profiling
+    def profile(self, enable: bool):
+        _check(lib().tdo_profile(self.h, int(bool(enable))))
+
+    def profile_read(self, kernel: str):
+        """(summed launch milliseconds, launch count) of a kernel group."""
+        ms, k = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().tdo_profile_read(self.h, kernel.encode(), ctypes.byref(ms), ctypes.byref(k)))
+        return float(ms.value), int(k.value)
 
     # ------------------------------------------------------------ entry points
     def connected(self, model: dict, cfg: torch.Tensor, kmax: int | None = None):

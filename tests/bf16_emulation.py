@@ -1,12 +1,16 @@
-"""CPU emulation of BF16 GEMM-operand rounding, used only to derive the BF16
-tolerance at the ill-conditioned stress scale.
+"""CPU emulations of the GPU path's rounding, used only to derive tolerances
+where the stated ones cannot hold for the arithmetic itself.
 
-It evaluates the same network as oracle.ansatz in FP64, but rounds every
-matrix-product operand to BF16 as the BF16 MFMA path does (activations entering
-QKV, scores, P.V, W_O and the MLP, and the weights).  The error of this
-emulation against the FP64 oracle is the error the BF16 arithmetic itself
-incurs; the GPU's BF16 result is required to stay within a small factor of it.
-It is not a reference for parity (the FP64 oracle is).
+* ``bf16``: the same network as oracle.ansatz evaluated in FP64, with every
+  matrix-product operand rounded to BF16 as the BF16 MFMA path does
+  (activations entering QKV, scores, P.V, W_O and the MLP, and the weights).
+  Differentiated by autograd, the casts also round the gradients flowing back
+  through those operands to BF16, which is what the BF16 backward does.
+* ``fp32``: the same network evaluated entirely in FP32 (torch on the CPU).
+
+The error of an emulation against the FP64 oracle is the error that precision
+incurs by itself; a GPU result is required to stay within a small factor of
+it.  It is not a reference for parity (the FP64 oracle is).
 """
 import math
 
@@ -14,36 +18,90 @@ import numpy as np
 import torch
 
 from oracle import ansatz as oa
+from oracle import lindblad as ol
 
 
-def _r(t):
+def _r16(t):
     return t.to(torch.bfloat16).to(torch.float64)
 
 
-def _z(theta, arch, bl, br):
-    p = oa.unflatten(theta, arch)
+def _ident(t):
+    return t
+
+
+def _z(p, arch, bl, br, R):
     x = oa.embed(p, 1 - 2 * bl, 1 - 2 * br)
     for l in range(arch.layers):
         B, N, d = x.shape
         H = arch.heads
         dh = d // H
-        xr = _r(x)
-        q = (xr @ _r(p[f"l{l}_wq"])).reshape(B, N, H, dh).transpose(1, 2)
-        k = (xr @ _r(p[f"l{l}_wk"])).reshape(B, N, H, dh).transpose(1, 2)
-        v = (xr @ _r(p[f"l{l}_wv"])).reshape(B, N, H, dh).transpose(1, 2)
-        s = (_r(q) @ _r(k).transpose(-1, -2)) / math.sqrt(dh)
+        xr = R(x)
+        q = (xr @ R(p[f"l{l}_wq"])).reshape(B, N, H, dh).transpose(1, 2)
+        k = (xr @ R(p[f"l{l}_wk"])).reshape(B, N, H, dh).transpose(1, 2)
+        v = (xr @ R(p[f"l{l}_wv"])).reshape(B, N, H, dh).transpose(1, 2)
+        s = (R(q) @ R(k).transpose(-1, -2)) / math.sqrt(dh)
         e = torch.exp(s - s.max(-1, keepdim=True).values)
-        o = (_r(e) @ _r(v)) / e.sum(-1, keepdim=True)
-        x = x + _r(o.transpose(1, 2).reshape(B, N, d)) @ _r(p[f"l{l}_wo"])
-        u = torch.clamp(_r(x) @ _r(p[f"l{l}_w1"]) + p[f"l{l}_b1"], min=0)
-        x = x + _r(u) @ _r(p[f"l{l}_w2"]) + p[f"l{l}_b2"]
+        o = (R(e) @ R(v)) / e.sum(-1, keepdim=True)
+        x = x + R(o.transpose(1, 2).reshape(B, N, d)) @ R(p[f"l{l}_wo"])
+        u = torch.clamp(R(x) @ R(p[f"l{l}_w1"]) + p[f"l{l}_b1"], min=0)
+        x = x + R(u) @ R(p[f"l{l}_w2"]) + p[f"l{l}_b2"]
     h = x.mean(1)
     f = h @ p["head_w"] + p["head_b"]
     return torch.complex(f[:, 0], f[:, 1])
 
 
-def log_rho_bf16(theta, arch, cfg, n):
+def _setup(prec):
+    if prec == "bf16":
+        return torch.float64, _r16
+    if prec == "fp32":
+        return torch.float32, _ident
+    raise ValueError(prec)
+
+
+def _log_rho(th, arch, cfg, n, prec):
+    dt, R = _setup(prec)
+    p = oa.unflatten(th, arch)
     a, b = oa.unpack_bits(cfg, n)
-    th = torch.as_tensor(np.asarray(theta, np.float64))
+    a, b = a.to(dt), b.to(dt)
+    return oa.symmetrise(_z(p, arch, a, b, R), _z(p, arch, b, a, R))
+
+
+def log_rho_emulated(theta, arch, cfg, n, prec):
+    dt, _ = _setup(prec)
+    th = torch.as_tensor(np.asarray(theta)).to(dt)
     with torch.no_grad():
-        return oa.symmetrise(_z(th, arch, a, b), _z(th, arch, b, a)).numpy()
+        return _log_rho(th, arch, cfg, n, prec).to(torch.complex128).numpy()
+
+
+def log_rho_bf16(theta, arch, cfg, n):
+    return log_rho_emulated(theta, arch, cfg, n, "bf16")
+
+
+def loss_grad_emulated(theta, arch, model, cfg, weights, mode, prec):
+    """(F, grad) of the cost at fixed samples (modes "A"/"B" as in oracle.vmc),
+    with the network evaluated and differentiated at the emulated precision."""
+    dt, _ = _setup(prec)
+    cdt = torch.complex64 if dt == torch.float32 else torch.complex128
+    cfg = np.asarray(cfg, dtype=np.uint64).reshape(-1, 2)
+    rows = ol.connected(model, cfg)
+    th = torch.tensor(np.asarray(theta), dtype=dt, requires_grad=True)
+    B = len(cfg)
+    allc = np.concatenate([cfg] + [r[0] for r in rows if len(r[0])], 0)
+    lr = _log_rho(th, arch, allc, model.n, prec)
+    lrx, off, Ls = lr[:B], B, []
+    for b in range(B):
+        k = len(rows[b][0])
+        c = torch.as_tensor(rows[b][1]).to(cdt)
+        Ls.append((c * torch.exp(lr[off:off + k] - lrx[b])).sum())
+        off += k
+    L = torch.stack(Ls)
+    w = torch.as_tensor(np.ones(B) if weights is None else np.asarray(weights), dtype=dt)
+    W = w.sum()
+    F = ((w * L.abs() ** 2).sum() / W).detach()
+    if mode == "A":
+        obj = (w * L.abs() ** 2).sum() / W
+    else:
+        r = w * torch.exp(2 * (lrx.real - lrx.real.detach()))
+        obj = (r * L.abs() ** 2 - F * r).sum() / W
+    (g,) = torch.autograd.grad(obj, th)
+    return float(F), g.double().numpy()
