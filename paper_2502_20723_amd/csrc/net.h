@@ -109,6 +109,28 @@ struct LayerPack {
   static constexpr int TOTAL = 4 * D * D + 2 * D * M;
 };
 
+// Row validity and configuration slot of lane row lr in block g (see the forward).
+struct RowMap {
+  int n, cpb;
+  bool span;
+  __device__ void at(int64_t g, int lr, int64_t E, int64_t& entry, int& pass, int& row_in_cfg, bool& valid) const {
+    if (span) {
+      const int64_t tile = g >> 1;
+      const int rb = (int)(g & 1);
+      entry = tile >> 1;
+      pass = (int)(tile & 1);
+      row_in_cfg = rb * 32 + lr;
+      valid = row_in_cfg < n && entry < E;
+    } else {
+      pass = (int)(g & 1);
+      const int slot = lr / n;
+      entry = (g >> 1) * cpb + slot;
+      row_in_cfg = lr % n;
+      valid = slot < cpb && entry < E;
+    }
+  }
+};
+
 // Exact ReLU of the feed-forward sub-layer.
 __device__ __forceinline__ float relu(float x) { return x > 0.f ? x : 0.f; }
 

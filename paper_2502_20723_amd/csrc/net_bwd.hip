@@ -96,28 +96,6 @@ __device__ __forceinline__ void store_tile(float* dst, const f32x16& v) {
   for (int q = 0; q < 4; ++q) p[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
 }
 
-// Row validity and configuration slot of lane row lr in block g (see the forward).
-struct RowMap {
-  int n, cpb;
-  bool span;
-  __device__ void at(int64_t g, int lr, int64_t E, int64_t& entry, int& pass, int& row_in_cfg, bool& valid) const {
-    if (span) {
-      const int64_t tile = g >> 1;
-      const int rb = (int)(g & 1);
-      entry = tile >> 1;
-      pass = (int)(tile & 1);
-      row_in_cfg = rb * 32 + lr;
-      valid = row_in_cfg < n && entry < E;
-    } else {
-      pass = (int)(g & 1);
-      const int slot = lr / n;
-      entry = (g >> 1) * cpb + slot;
-      row_in_cfg = lr % n;
-      valid = slot < cpb && entry < E;
-    }
-  }
-};
-
 // ------------------------------------------------------------------ MLP backward
 template <class P, int D>
 __global__ void __launch_bounds__(256) k_bwd_mlp(BwdArgs a) {

@@ -1,0 +1,295 @@
+// Backward of the residual feed-forward sub-layer y = x + relu(x W1 + b1) W2 + b2
+// for width 64 with BF16 MFMA operands (FP32 accumulation):
+//   u = x W1 + b1 (recomputed), dh = g W2^T, du = dh [u > 0], dx = g + du W1^T,
+//   dW1 += x^T du, dW2 += relu(u)^T g, db1 += sum du, db2 += sum g.
+//
+// Work decomposition.  A workgroup (4 waves) walks 64-row tiles (two 32-row
+// blocks of the activation layout) and keeps the weight gradients of the
+// whole launch in registers: wave w owns the hidden units
+// [w M/4, (w+1) M/4), i.e. its columns of dW1 and rows of dW2, so no
+// gradient is ever added through memory until the launch ends.  Per tile:
+//   1. the tile's x and g are staged in LDS twice: row-major (operands of
+//      the contractions over features) and transposed with the rows of each
+//      16-row group reordered so that one 16-byte read returns exactly the
+//      rows an MFMA result tile holds in its values (operands of the
+//      contractions over rows);
+//   2. each wave recomputes u and dh for its hidden units in the
+//      (row x hidden) orientation, whose registers are directly the row-
+//      contraction operands of dW1 and dW2, and writes du to LDS;
+//   3. each wave forms one 32x32 tile of dx = g + du W1^T from the du of all
+//      hidden units.
+// The workgroup's gradients are written once per launch to its slot of the
+// partial buffer [2DM + M + D] (same layout as the generic kernel), and the
+// slots are summed in FP64 afterwards.
+#include "common.h"
+#include "net.h"
+#include "netapi.h"
+
+namespace tdo {
+
+namespace {
+
+constexpr int RT = 64;  // rows per tile
+constexpr int XS = 72;  // bf16 row stride of the 64-wide LDS tiles (144 bytes: conflict-free 16-byte reads)
+
+// Position of tile row `row` in the transposed LDS tiles: inside each group
+// of 16 rows the two middle quads are swapped, so that positions
+// 16s + 8h + t (t < 8) hold rows tile_idx(8s + t, h) of the MFMA result layout.
+__device__ __forceinline__ int perm16(int row) {
+  const int q = row & 15;
+  return (row & ~15) | ((q & 4) << 1) | ((q & 8) >> 1) | (q & 3);
+}
+
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+__device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x8 op8(const f32x16& v, int s) {
+  bf16x8 o;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) o[t] = (__bf16)v[8 * s + t];
+  return o;
+}
+
+}  // namespace
+
+// Gradient entering the sub-layer for (block gb, feature block ob, lane l):
+// 16 values, features 32 ob + tile_idx(r, l/32) of row l%32 of the block.
+template <int NB>
+__device__ __forceinline__ void grad_tile(const BwdArgs& a, const RowMap& rm, int64_t E, int64_t gb, int ob, int l,
+                                          float (&g)[16]) {
+  if (a.g_in) {
+    const float4* p = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + ob) * 64 + l) * 16);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 t = p[q];
+      g[4 * q] = t.x; g[4 * q + 1] = t.y; g[4 * q + 2] = t.z; g[4 * q + 3] = t.w;
+    }
+    return;
+  }
+  // last layer: g = (dF0 head_w[:,0] + dF1 head_w[:,1]) / n from the pooled head
+  int64_t e;
+  int pass, ric;
+  bool valid;
+  rm.at(gb, l & 31, E, e, pass, ric, valid);
+  float s0 = 0.f, s1 = 0.f;
+  if (valid) {
+    s0 = a.seeds[(e * 2 + pass) * 2] / (float)a.n;
+    s1 = a.seeds[(e * 2 + pass) * 2 + 1] / (float)a.n;
+  }
+  const int h = l >> 5;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int f = 32 * ob + tile_idx(r, h);
+    g[r] = f < a.d_real ? s0 * a.head_w[2 * f] + s1 * a.head_w[2 * f + 1] : 0.f;
+  }
+}
+
+template <int M>
+__global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
+  constexpr int D = 64, NB = 2, HW = M / 4, HT = HW / 32, KS = M / 16, DUS = M + 8;
+  static_assert(HT >= 1 && HT <= 2 && HW % 32 == 0, "hidden width 128 or 256");
+  extern __shared__ __align__(16) char smem[];
+  __bf16* XA = reinterpret_cast<__bf16*>(smem);  // [RT][XS]   x, row-major
+  __bf16* XT = XA + RT * XS;                      // [D][XS]    x^T, permuted rows
+  __bf16* GA = XT + D * XS;                       // [RT][XS]   g, row-major
+  __bf16* GT = GA + RT * XS;                      // [D][XS]    g^T, permuted rows
+  __bf16* DU = GT + D * XS;                       // [RT][DUS]  du, row-major
+  __bf16* W1s = DU + RT * DUS;                    // [D][DUS]   W1 (operand of dx = du W1^T)
+  float* db2s = reinterpret_cast<float*>(W1s + D * DUS);  // [D]
+
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31, w = t >> 6;
+  const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
+  const RowMap rm{a.n, a.cpb, a.span != 0};
+  const int64_t nblk = a.span ? 4 * E : 2 * ((E + a.cpb - 1) / a.cpb);
+  const int64_t ntile = (nblk + 1) / 2;
+  if (t < D) db2s[t] = 0.f;
+
+  // ---- weights of this wave, as BF16 MFMA operands (read once per launch)
+  const int hid0 = HW * w;  // first hidden unit owned by this wave
+  bf16x8 w1b[HT][4], w2b[HT][4];
+#pragma unroll
+  for (int nt = 0; nt < HT; ++nt)
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int hid = hid0 + 32 * nt + lr, f = 16 * s + 8 * h + k;
+        w1b[nt][s][k] = (__bf16)a.w1[f * M + hid];  // B[k = in][n = hidden] = W1[in][hidden]
+        w2b[nt][s][k] = (__bf16)a.w2[hid * D + f];  // B[k = out][n = hidden] = W2[hidden][out]
+      }
+  const int rb3 = w >> 1, it3 = w & 1;  // tile of dx formed by this wave
+  for (int i = t; i < D * M; i += 256) W1s[(i / M) * DUS + i % M] = (__bf16)a.w1[i];
+  __syncthreads();  // W1s and db2s initialised before any use
+  float bias[HT];
+#pragma unroll
+  for (int nt = 0; nt < HT; ++nt) bias[nt] = a.b1[hid0 + 32 * nt + lr];
+
+  f32x16 dW1[NB][HT], dW2[HT][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int nt = 0; nt < HT; ++nt) { dW1[i][nt] = f32x16{}; dW2[nt][i] = f32x16{}; }
+  float db1[HT], db2[16];
+#pragma unroll
+  for (int nt = 0; nt < HT; ++nt) db1[nt] = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) db2[r] = 0.f;
+
+  // staging role of this thread: block sb of the tile, feature block sob, lane sl
+  const int sb = t >> 7, sob = (t >> 6) & 1, sl = lane, srow = 32 * sb + (sl & 31), sh = sl >> 5;
+
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    // ---- 1. stage x and g of the tile
+    {
+      const int64_t gb = 2 * tile + sb;
+      float x[16], g[16];
+      if (gb < nblk) {
+        const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_mid) + ((gb * NB + sob) * 64 + sl) * 16;
+        const bf16x8 x0 = ld8(xs), x1 = ld8(xs + 8);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) { x[k] = (float)x0[k]; x[8 + k] = (float)x1[k]; }
+        grad_tile<NB>(a, rm, E, gb, sob, sl, g);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = g[r] = 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) db2[r] += g[r];
+      const int pr = perm16(srow);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int f0 = 32 * sob + 8 * j + 4 * sh;
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 xv, gv;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          xv[c] = (__bf16)x[4 * j + c];
+          gv[c] = (__bf16)g[4 * j + c];
+          XT[(f0 + c) * XS + pr] = xv[c];
+          GT[(f0 + c) * XS + pr] = gv[c];
+        }
+        *reinterpret_cast<bf16x4*>(XA + srow * XS + f0) = xv;
+        *reinterpret_cast<bf16x4*>(GA + srow * XS + f0) = gv;
+      }
+    }
+    __syncthreads();
+
+    // ---- 2. hidden units of this wave: u, dh, du; dW1, dW2, db1; du to LDS
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      f32x16 u[HT], dh[HT];
+#pragma unroll
+      for (int nt = 0; nt < HT; ++nt) { u[nt] = f32x16{}; dh[nt] = f32x16{}; }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bf16x8 xa = ld8(XA + (32 * rb + lr) * XS + 16 * s + 8 * h);
+        const bf16x8 ga = ld8(GA + (32 * rb + lr) * XS + 16 * s + 8 * h);
+#pragma unroll
+        for (int nt = 0; nt < HT; ++nt) {
+          u[nt] = mfma16(xa, w1b[nt][s], u[nt]);    // (row x hidden): lane -> hidden, values -> rows
+          dh[nt] = mfma16(ga, w2b[nt][s], dh[nt]);
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < HT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float uu = u[nt][r] + bias[nt];
+          const float d = uu > 0.f ? dh[nt][r] : 0.f;
+          u[nt][r] = uu > 0.f ? uu : 0.f;  // relu(u)
+          dh[nt][r] = d;                   // du
+          db1[nt] += d;
+        }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int pos = 32 * rb + 16 * s + 8 * h;
+        bf16x8 xt[NB], gt[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          xt[i] = ld8(XT + (32 * i + lr) * XS + pos);
+          gt[i] = ld8(GT + (32 * i + lr) * XS + pos);
+        }
+#pragma unroll
+        for (int nt = 0; nt < HT; ++nt) {
+          const bf16x8 duo = op8(dh[nt], s), ho = op8(u[nt], s);
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            dW1[i][nt] = mfma16(xt[i], duo, dW1[i][nt]);  // (in x hidden)
+            dW2[nt][i] = mfma16(ho, gt[i], dW2[nt][i]);   // (hidden x out)
+          }
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < HT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) DU[(32 * rb + tile_idx(r, h)) * DUS + hid0 + 32 * nt + lr] = (__bf16)dh[nt][r];
+    }
+    __syncthreads();
+
+    // ---- 3. dx tile (rows of block rb3, features of block it3) = g + du W1^T
+    {
+      const int64_t gb = 2 * tile + rb3;
+      f32x16 acc = f32x16{};
+#pragma unroll
+      for (int s = 0; s < KS; ++s)  // A[m = in][k = hidden] = W1, B[k = hidden][n = row] = du
+        acc = mfma16(ld8(W1s + (32 * it3 + lr) * DUS + 16 * s + 8 * h), ld8(DU + (32 * rb3 + lr) * DUS + 16 * s + 8 * h), acc);
+      if (gb < nblk) {
+        float g[16];
+        grad_tile<NB>(a, rm, E, gb, it3, lane, g);
+        float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + it3) * 64 + lane) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          dst[q] = make_float4(acc[4 * q] + g[4 * q], acc[4 * q + 1] + g[4 * q + 1], acc[4 * q + 2] + g[4 * q + 2],
+                               acc[4 * q + 3] + g[4 * q + 3]);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- write this workgroup's gradients: dW1 [D][M], dW2 [M][D], db1 [M], db2 [D]
+  float* part = a.partial + (int64_t)blockIdx.x * (2 * D * M + M + D);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int nt = 0; nt < HT; ++nt)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        part[(32 * i + tile_idx(r, h)) * M + hid0 + 32 * nt + lr] = dW1[i][nt][r];
+        part[D * M + (hid0 + 32 * nt + tile_idx(r, h)) * D + 32 * i + lr] = dW2[nt][i][r];
+      }
+#pragma unroll
+  for (int nt = 0; nt < HT; ++nt) {
+    const float v = db1[nt] + __shfl_xor(db1[nt], 32, 64);
+    if (h == 0) part[2 * D * M + hid0 + 32 * nt + lr] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) atomicAdd(db2s + 32 * sob + tile_idx(r, sh), db2[r]);
+  __syncthreads();
+  if (t < D) part[2 * D * M + M + t] = db2s[t];
+}
+
+size_t bwd_mlp_bf16_lds(int M) {
+  return (size_t)(2 * RT * XS + 2 * 64 * XS + (RT + 64) * (M + 8)) * sizeof(__bf16) + 64 * sizeof(float);
+}
+
+bool bwd_mlp_bf16_supported(int d, int D, int M) { return d == 64 && D == 64 && (M == 128 || M == 256); }
+
+int32_t launch_bwd_mlp_bf16(const BwdArgs& a, int blocks, hipStream_t st) {
+  const size_t lds = bwd_mlp_bf16_lds(a.M);
+  auto go = [&](auto kern) -> int32_t {
+    TDO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
+    TDO_HIP(hipGetLastError());
+    return TDO_OK;
+  };
+  switch (a.M) {
+    case 128: return go(k_bwd_mlp_bf16<128>);
+    case 256: return go(k_bwd_mlp_bf16<256>);
+    default: return set_error(TDO_EUNSUPPORTED, "BF16 feed-forward backward: mlp width %d", a.M);
+  }
+}
+
+}  // namespace tdo

@@ -53,6 +53,8 @@ struct BwdArgs {
   const void* wf;               // this layer's forward fragments
   const void* wb;               // this layer's transposed fragments
   const float* b1;              // [M]
+  const float* w1;              // this layer's W1 [d][mlp] and W2 [mlp][d] in the flat FP32 parameters
+  const float* w2;
   const void* save_x;           // layer input
   const void* save_mid;         // feed-forward input
   const float* g_in;            // incoming gradient [blocks][D/32][64][16] (NULL: from seeds)
@@ -67,6 +69,9 @@ struct BwdArgs {
 };
 
 size_t bwd_mlp_lds(int D, int M);
+// Feed-forward backward with BF16 operands and per-wave register gradients (width 64).
+bool bwd_mlp_bf16_supported(int d, int D, int M);
+int32_t launch_bwd_mlp_bf16(const BwdArgs& a, int blocks, hipStream_t st);
 int32_t launch_bwd_mlp(const BwdArgs& a, bool bf16, int D, int blocks, hipStream_t st);
 int32_t launch_bwd_attn(const BwdArgs& a, bool bf16, int D, int DH, int blocks, hipStream_t st);
 int32_t launch_bwd_head(bool bf16, int D, const void* save_last, const float* seeds, const int64_t* E_dev,

@@ -137,6 +137,8 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
     a.b1 = w.b1 + (size_t)l * M;
     a.save_x = static_cast<const char*>(sv.x) + (size_t)l * sv.layer_bytes;
     a.save_mid = static_cast<const char*>(sv.mid) + (size_t)l * sv.layer_bytes;
+    a.w1 = params + pp.off_layer0 + (int64_t)l * pp.layer_stride + 4LL * pp.d * pp.d;
+    a.w2 = a.w1 + (int64_t)pp.d * pp.mlp + pp.mlp;
     a.head_w = w.head_w;
     a.partial = bb.partial;
     a.n_entries_dev = E_dev;
@@ -157,7 +159,10 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
     TDO_TRY(fill(bb.attn_acc, alen, 0.0, st));
     {
       ProfScope ps(np.prof, "bwd_mlp", st);
-      TDO_TRY(launch_bwd_mlp(a, np.bf16, D, bb.nparts, st));
+      if (np.bf16 && bwd_mlp_bf16_supported(pp.d, D, M))
+        TDO_TRY(launch_bwd_mlp_bf16(a, bb.nparts, st));
+      else
+        TDO_TRY(launch_bwd_mlp(a, np.bf16, D, bb.nparts, st));
     }
     TDO_TRY(launch_reduce_partials(bb.partial, bb.nparts, mlen, bb.mlp_acc, st));
     // attention sub-layer: gb -> ga
