@@ -21,7 +21,7 @@ output words r0, r1, r2:
   accept         iff (r2 + 0.5) * 2^-32 < exp(2 Re(log rho(x') - log rho(x))).
 One sweep is 2N proposals; a sample is recorded after each sweep.
 
-Parity: pinned in tests/test_oracle_sampler.py by a chi-square test of the
+Parity: pinned in tests/test_oracle_philox_sampler.py by a chi-square test of the
 visit frequencies against the exactly enumerated |rho|^2 at N = 3, and by the
 pure random walk (every move accepted) when log rho is constant.
 """
