@@ -1,0 +1,332 @@
+// Backward of the residual multi-head attention sub-layer y = x + concat_h(O_h) W_O,
+// O_h = softmax(Q_h K_h^T / sqrt(dh)) V_h, Q = x Wq, K = x Wk, V = x Wv
+// (Eq. attn-head-appendix), for width 64 with BF16 MFMA operands and FP32
+// accumulation, chains of n <= 32 sites (configurations never span blocks):
+//   dO = g W_O^T;  per head: dP = dO V^T, dS = P (dP - rowsum(P dP)) / sqrt(dh),
+//   dQ = dS K, dK = dS^T Q, dV = P^T dO;  dx = g + dQ Wq^T + dK Wk^T + dV Wv^T;
+//   dW_O += O^T g, dWq += x^T dQ, dWk += x^T dK, dWv += x^T dV.
+//
+// Work decomposition.  A workgroup of 4 waves walks tiles of 4 blocks of 32
+// rows; wave w handles block w of the tile, then owns one weight gradient
+// (w = 0..3: Wq, Wk, Wv, W_O) accumulated in registers for the whole launch.
+//
+// Block phase (one wave).  Every contraction over keys or queries needs its
+// operands with lanes enumerating features and values enumerating rows, the
+// transpose of what the projections give.  The projections are therefore
+// formed in both orientations (the same weight fragments serve as A or B
+// operand), and the per-head probability and dS tiles, computed query-major,
+// are transposed to key-major through LDS as BF16 (in a part of the block's
+// staging area that is not yet in use).
+//
+// Gradient phase (all waves).  x, g, O, dQ, dK, dV of each block are staged
+// in LDS as [feature][row] BF16 with the rows of each 16-row group in the
+// order of the MFMA result layout (two middle quads swapped), so that one
+// 16-byte read is a row-contraction operand.  After a workgroup barrier, wave
+// w adds the tile's 4 x 32 rows into its gradient.  Each workgroup writes its
+// four gradients once per launch to its partial slot [4 D^2] (Wq, Wk, Wv as
+// (in, attention feature), W_O as (attention feature, out)); the slots are
+// summed in FP64 afterwards.
+#include "common.h"
+#include "net.h"
+#include "netapi.h"
+
+namespace tdo {
+
+namespace {
+
+constexpr int FS = 40;               // row stride (bf16) of a staged [feature][row] matrix: conflict-free 16-byte reads
+constexpr int MAT = 64 * FS;         // one staged matrix
+enum { SX = 0, SG = 1, SQ = 2, SK = 3, SV = 4, SO = 5, NSTAGE = 6 };
+
+__device__ __forceinline__ int perm16(int row) {
+  const int q = row & 15;
+  return (row & ~15) | ((q & 4) << 1) | ((q & 8) >> 1) | (q & 3);
+}
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+__device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 op8(const f32x16& v, int s) {
+  bf16x8 o;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) o[t] = (__bf16)v[8 * s + t];
+  return o;
+}
+__device__ __forceinline__ bf16x8 op8m(const f32x16& v, int s, bool keep) {
+  bf16x8 o;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) o[t] = (__bf16)(keep ? v[8 * s + t] : 0.f);
+  return o;
+}
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// R-layout tile (lane -> row, values -> features f0 + tile_idx(r, h)) into a staged [feature][row] matrix.
+__device__ __forceinline__ void stage_rows(__bf16* m, int f0, const f32x16& v, int lr, int h) {
+  const int pr = perm16(lr);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) m[(f0 + tile_idx(r, h)) * FS + pr] = (__bf16)v[r];
+}
+
+}  // namespace
+
+template <int DH>
+__global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
+  constexpr int D = 64, NB = 2, ST = 2, HPB = 32 / DH;
+  extern __shared__ __align__(16) char smem[];
+  __bf16* Wl = reinterpret_cast<__bf16*>(smem);      // Wq, Wk, Wv, W_O^T fragments [4][D*D]
+  __bf16* stg = Wl + 4 * D * D;                       // [4 blocks][NSTAGE][MAT]
+
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31, w = t >> 6;
+  {
+    const int4* sf = reinterpret_cast<const int4*>(a.wf);
+    const int4* sb = reinterpret_cast<const int4*>(a.wb);
+    int4* dl = reinterpret_cast<int4*>(Wl);
+    for (int i = t; i < 3 * D * D / 8; i += 256) dl[i] = sf[i];
+    for (int i = t; i < D * D / 8; i += 256) dl[3 * D * D / 8 + i] = sb[3 * D * D / 8 + i];
+  }
+  const __bf16 *Wq = Wl, *Wk = Wl + D * D, *Wv = Wl + 2 * D * D, *WoT = Wl + 3 * D * D;
+  const __bf16* Wb = reinterpret_cast<const __bf16*>(a.wb);
+  const __bf16 *WqT = Wb, *WkT = Wb + D * D, *WvT = Wb + 2 * D * D;  // global (L2)
+  __syncthreads();
+
+  const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
+  const int n = a.n, cpb = a.cpb;
+  const int64_t nblk = 2 * ((E + cpb - 1) / cpb);
+  const int64_t ntile = (nblk + 3) / 4;
+  const float sc = a.score_scale, isd = a.inv_sqrt_dh;
+  const bool masked = a.masked != 0;
+  // valid (query, key) pairs of this lane's row lr against rows tile_idx(r, h): same configuration
+  // slot, slot < cpb (symmetric, so the same bits serve query-major and key-major tiles)
+  uint32_t okbits = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int other = tile_idx(r, h) / n;
+    okbits |= (other == lr / n && other < cpb) ? (1u << r) : 0u;
+  }
+
+  f32x16 dW[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) dW[i][j] = f32x16{};
+
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    // ================= block phase: block gb of wave w
+    const int64_t gb = 4 * tile + w;
+    const bool valid = gb < nblk;
+    __bf16* S = stg + w * NSTAGE * MAT;
+    // x (layer input) and g (gradient of the sub-layer output) of the block, lane -> row
+    auto load_xg = [&](int ib, f32x16& xr, f32x16& gr) {
+      if (valid) {
+        const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_x) + ((gb * NB + ib) * 64 + lane) * 16;
+        const bf16x8 x0 = ld8(xs), x1 = ld8(xs + 8);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) { xr[k] = (float)x0[k]; xr[8 + k] = (float)x1[k]; }
+        const float4* gs = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + ib) * 64 + lane) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 v = gs[q];
+          gr[4 * q] = v.x; gr[4 * q + 1] = v.y; gr[4 * q + 2] = v.z; gr[4 * q + 3] = v.w;
+        }
+      } else {
+        xr = f32x16{};
+        gr = f32x16{};
+      }
+    };
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
+      f32x16 xr, gr;
+      load_xg(ib, xr, gr);
+      stage_rows(S + SX * MAT, 32 * ib, xr, lr, h);
+      stage_rows(S + SG * MAT, 32 * ib, gr, lr, h);
+    }
+
+#pragma unroll 1
+    for (int hb = 0; hb < NB; ++hb) {
+      // projections of the 32 attention features of head block hb, both orientations:
+      // *R: lane -> row, values -> features;  *F: lane -> feature, values -> rows
+      f32x16 QR = {}, KR = {}, VR = {}, OR = {}, QF = {}, KF = {}, VF = {}, OF = {};
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        f32x16 xr, gr;
+        load_xg(ib, xr, gr);
+        bf16x8 xo[ST], go[ST];
+#pragma unroll
+        for (int s = 0; s < ST; ++s) { xo[s] = op8(xr, s); go[s] = op8(gr, s); }
+#pragma unroll
+        for (int s = 0; s < ST; ++s) {
+          const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
+          const bf16x8 wq = ld8(Wq + f * 8), wk = ld8(Wk + f * 8), wv = ld8(Wv + f * 8), wo = ld8(WoT + f * 8);
+          QR = mfma16(wq, xo[s], QR);
+          QF = mfma16(xo[s], wq, QF);
+          KR = mfma16(wk, xo[s], KR);
+          KF = mfma16(xo[s], wk, KF);
+          VR = mfma16(wv, xo[s], VR);
+          VF = mfma16(xo[s], wv, VF);
+          OR = mfma16(wo, go[s], OR);  // dO, R
+          OF = mfma16(go[s], wo, OF);  // dO, F
+        }
+      }
+      // feature-major projections as BF16 operands (masked to one head below); score scale folded into Q
+      bf16x8 QFb[ST], KFb[ST], VFb[ST], OFb[ST];
+#pragma unroll
+      for (int s = 0; s < ST; ++s) { QFb[s] = op8(QF, s); KFb[s] = op8(KF, s); VFb[s] = op8(VF, s); OFb[s] = op8(OF, s); }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) QR[r] *= sc;
+      // key-major transposes of P and dS go through the part of this block's O and dV staging
+      // that head block hb fills only after its heads are done
+      __bf16* TP = S + SO * MAT + 32 * hb * FS;
+      __bf16* TS = S + SV * MAT + 32 * hb * FS;
+      f32x16 dQR = {}, dKR = {}, dVR = {}, AOF = {};  // dQ, dK, dV (R) and the attention output O (F)
+#pragma unroll
+      for (int j = 0; j < HPB; ++j) {
+        const bool mine = (lr / DH) == j;
+        // query-major tiles: lane -> query lr, values -> keys tile_idx(r, h)
+        f32x16 sq = PBF16::scores<DH>(KR, QR, j, f32x16{});
+        f32x16 dpq = PBF16::scores<DH>(VR, OR, j, f32x16{});
+        float m = -INFINITY;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          if (masked && !((okbits >> r) & 1u)) sq[r] = -INFINITY;
+          m = fmaxf(m, sq[r]);
+        }
+        m = fmaxf(m, __shfl_xor(m, 32, 64));
+        const float mm = (m == -INFINITY) ? 0.f : m;  // a query with no key keeps P = 0
+        float l = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          sq[r] = __builtin_amdgcn_exp2f(sq[r] - mm);
+          l += sq[r];
+        }
+        l += __shfl_xor(l, 32, 64);
+        const float il = l > 0.f ? 1.0f / l : 0.f;
+        float dl = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          sq[r] *= il;  // P
+          dl += sq[r] * dpq[r];
+        }
+        dl += __shfl_xor(dl, 32, 64);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dpq[r] = sq[r] * (dpq[r] - dl) * isd;  // dS
+        bf16x8 Pq[ST], Sq[ST];
+#pragma unroll
+        for (int s = 0; s < ST; ++s) { Pq[s] = op8(sq, s); Sq[s] = op8(dpq, s); }
+        // transpose P and dS: [key][query position], read back key-major
+        wave_sync();
+        {
+          const int pq = perm16(lr);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            TP[tile_idx(r, h) * FS + pq] = Pq[r >> 3][r & 7];
+            TS[tile_idx(r, h) * FS + pq] = Sq[r >> 3][r & 7];
+          }
+        }
+        wave_sync();
+        bf16x8 Pk[ST], Sk[ST];
+#pragma unroll
+        for (int s = 0; s < ST; ++s) {
+          Pk[s] = ld8(TP + lr * FS + 16 * s + 8 * h);  // lane -> key, values -> queries
+          Sk[s] = ld8(TS + lr * FS + 16 * s + 8 * h);
+        }
+#pragma unroll
+        for (int s = 0; s < ST; ++s) {
+          const bf16x8 z = {};
+          AOF = mfma16(Pq[s], mine ? VFb[s] : z, AOF);  // O[q][f]  = sum_k P[q][k] V[k][f]
+          dQR = mfma16(mine ? KFb[s] : z, Sq[s], dQR);  // dQ[q][f] = sum_k dS[q][k] K[k][f]
+          dKR = mfma16(mine ? QFb[s] : z, Sk[s], dKR);  // dK[k][f] = sum_q dS[q][k] Q[q][f]
+          dVR = mfma16(mine ? OFb[s] : z, Pk[s], dVR);  // dV[k][f] = sum_q P[q][k] dO[q][f]
+        }
+      }
+      wave_sync();  // the transposes are consumed before the staging below reuses their space
+      // stage dQ, dK, dV (R layout -> [feature][row]) and O (F layout: two 16-byte writes per lane)
+      stage_rows(S + SQ * MAT, 32 * hb, dQR, lr, h);
+      stage_rows(S + SK * MAT, 32 * hb, dKR, lr, h);
+      stage_rows(S + SV * MAT, 32 * hb, dVR, lr, h);
+#pragma unroll
+      for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + (32 * hb + lr) * FS + 16 * s + 8 * h) = op8(AOF, s);
+      // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T, the terms of head block hb added through the output
+      // buffer (each lane rereads only what it wrote)
+      if (valid) {
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) {
+          f32x16 acc;
+          const float4* src = reinterpret_cast<const float4*>((hb == 0 ? a.g_in : a.g_out) + ((gb * NB + ob) * 64 + lane) * 16);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 v = src[q];
+            acc[4 * q] = v.x; acc[4 * q + 1] = v.y; acc[4 * q + 2] = v.z; acc[4 * q + 3] = v.w;
+          }
+#pragma unroll
+          for (int s = 0; s < ST; ++s) {
+            const int f = ((ob * NB + hb) * ST + s) * 64 + lane;
+            acc = mfma16(ld8(WqT + f * 8), op8(dQR, s), acc);
+            acc = mfma16(ld8(WkT + f * 8), op8(dKR, s), acc);
+            acc = mfma16(ld8(WvT + f * 8), op8(dVR, s), acc);
+          }
+          float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + ob) * 64 + lane) * 16);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dst[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+        }
+      }
+    }
+    __syncthreads();
+
+    // ================= gradient phase: wave w adds the tile's rows into its weight gradient
+    {
+      const int am = (w < 3) ? SX : SO;       // A operand: x (for Wq, Wk, Wv) or O (for W_O)
+      const int bm = (w < 3) ? SQ + w : SG;   // B operand: dQ, dK, dV or g
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const __bf16* A = stg + (b * NSTAGE + am) * MAT;
+        const __bf16* B = stg + (b * NSTAGE + bm) * MAT;
+#pragma unroll
+        for (int s = 0; s < ST; ++s) {
+          bf16x8 av[NB], bv[NB];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            av[i] = ld8(A + (32 * i + lr) * FS + 16 * s + 8 * h);
+            bv[i] = ld8(B + (32 * i + lr) * FS + 16 * s + 8 * h);
+          }
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) dW[i][j] = mfma16(av[i], bv[j], dW[i][j]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  float* part = a.partial + (int64_t)blockIdx.x * 4 * D * D + (int64_t)w * D * D;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) part[(32 * i + tile_idx(r, h)) * D + 32 * j + lr] = dW[i][j][r];
+}
+
+size_t bwd_attn_bf16_lds() {
+  return (size_t)(4 * 64 * 64 + 4 * NSTAGE * MAT) * sizeof(__bf16);
+}
+
+bool bwd_attn_bf16_supported(int d, int D, int DH, bool span) { return d == 64 && D == 64 && !span && (DH == 8 || DH == 16); }
+
+int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t st) {
+  const size_t lds = bwd_attn_bf16_lds();
+  auto go = [&](auto kern) -> int32_t {
+    TDO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
+    TDO_HIP(hipGetLastError());
+    return TDO_OK;
+  };
+  if (DH == 8) return go(k_bwd_attn_bf16<8>);
+  if (DH == 16) return go(k_bwd_attn_bf16<16>);
+  return set_error(TDO_EUNSUPPORTED, "BF16 attention backward: head width %d", DH);
+}
+
+}  // namespace tdo

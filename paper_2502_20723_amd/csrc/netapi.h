@@ -72,6 +72,9 @@ size_t bwd_mlp_lds(int D, int M);
 // Feed-forward backward with BF16 operands and per-wave register gradients (width 64).
 bool bwd_mlp_bf16_supported(int d, int D, int M);
 int32_t launch_bwd_mlp_bf16(const BwdArgs& a, int blocks, hipStream_t st);
+// Attention backward with BF16 operands and per-wave register gradients (width 64, n <= 32).
+bool bwd_attn_bf16_supported(int d, int D, int DH, bool span);
+int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t st);
 int32_t launch_bwd_mlp(const BwdArgs& a, bool bf16, int D, int blocks, hipStream_t st);
 int32_t launch_bwd_attn(const BwdArgs& a, bool bf16, int D, int DH, int blocks, hipStream_t st);
 int32_t launch_bwd_head(bool bf16, int D, const void* save_last, const float* seeds, const int64_t* E_dev,

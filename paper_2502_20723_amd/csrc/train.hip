@@ -171,7 +171,10 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
     a.g_out = bb.ga;
     {
       ProfScope ps(np.prof, "bwd_attn", st);
-      TDO_TRY(launch_bwd_attn(a, np.bf16, D, np.DH, bb.nparts, st));
+      if (np.bf16 && bwd_attn_bf16_supported(pp.d, D, np.DH, np.span))
+        TDO_TRY(launch_bwd_attn_bf16(a, np.DH, bb.nparts, st));
+      else
+        TDO_TRY(launch_bwd_attn(a, np.bf16, D, np.DH, bb.nparts, st));
     }
     TDO_TRY(launch_reduce_partials(bb.partial, bb.nparts, alen, bb.attn_acc, st));
     TDO_TRY(launch_scatter_layer(bb.mlp_acc, bb.attn_acc, pp.d, D, M, 1.0, gt + pp.off_layer0 + l * pp.layer_stride, st));
