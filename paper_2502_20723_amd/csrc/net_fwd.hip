@@ -119,6 +119,24 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
   const int64_t ntiles = SPAN ? 2 * E : 2 * ((E + cpb - 1) / cpb);
   const float sc = a.score_scale;  // log2(e)/sqrt(dh)
 
+  // valid (query row qb*32+lr, key row kb*32+tile_idx(r, h)) pairs as bit r of okbits[qb][kb]
+  uint32_t okbits[NBR][NBR];
+#pragma unroll
+  for (int qb = 0; qb < NBR; ++qb)
+#pragma unroll
+    for (int kb = 0; kb < NBR; ++kb) {
+      uint32_t bits = 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int key = kb * 32 + tile_idx(r, h);
+        bool ok;
+        if (SPAN) ok = key < n;
+        else ok = a.masked ? ((key / n) == (SPAN ? 0 : lr / n) && (key / n) < cpb) : true;
+        bits |= ok ? (1u << r) : 0u;
+      }
+      okbits[qb][kb] = bits;
+    }
+
   for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; tile < ntiles;
        tile += (int64_t)gridDim.x * (blockDim.x >> 6)) {
     const int pass = (int)(tile & 1);
@@ -212,13 +230,22 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
             v[rb] = P::mma(xo[rb][ib][s], ld_frag<P>(Wv, f, lane), v[rb]);  // (row x feature)
           }
       }
+      // score scale folded into q; V as operands (lane -> feature), masked to one head below
+#pragma unroll
+      for (int rb = 0; rb < NBR; ++rb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) q[rb][r] *= sc;
+      op_t vop[NBR][ST];
+#pragma unroll
+      for (int kb = 0; kb < NBR; ++kb)
+#pragma unroll
+        for (int s = 0; s < ST; ++s) vop[kb][s] = P::op(v[kb], s);
       f32x16 o[NBR];
       float invl[NBR][HPB];
 #pragma unroll
       for (int rb = 0; rb < NBR; ++rb) o[rb] = f32x16{};
 #pragma unroll
       for (int j = 0; j < HPB; ++j) {
-        // V fragments restricted to head j (A operand: lane -> feature lr)
         const bool mine = (lr / DH) == j;
 #pragma unroll
         for (int qb = 0; qb < NBR; ++qb) {
@@ -229,22 +256,18 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
             st[kb] = P::template scores<DH>(k[kb], q[qb], j, f32x16{});
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-              const int key = kb * 32 + tile_idx(r, h);
-              bool ok;
-              if (SPAN) ok = key < n;
-              else ok = a.masked ? ((key / n) == rslot[qb] && (key / n) < cpb) : true;
-              const float s2 = ok ? st[kb][r] * sc : -INFINITY;
-              st[kb][r] = s2;
-              m = fmaxf(m, s2);
+              if (!((okbits[qb][kb] >> r) & 1u)) st[kb][r] = -INFINITY;
+              m = fmaxf(m, st[kb][r]);
             }
           }
           m = fmaxf(m, __shfl_xor(m, 32, 64));
+          const float mm = (m == -INFINITY) ? 0.f : m;  // a row with no key keeps P = 0
           float l = 0.f;
 #pragma unroll
           for (int kb = 0; kb < NBR; ++kb)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-              const float p = (m == -INFINITY) ? 0.f : exp2f(st[kb][r] - m);
+              const float p = __builtin_amdgcn_exp2f(st[kb][r] - mm);
               st[kb][r] = p;
               l += p;
             }
@@ -253,11 +276,7 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
 #pragma unroll
           for (int kb = 0; kb < NBR; ++kb)
 #pragma unroll
-            for (int s = 0; s < ST; ++s) {
-              const op_t vv = P::op(v[kb], s);
-              const op_t va = mine ? vv : op_t{};
-              o[qb] = P::mma(va, P::op(st[kb], s), o[qb]);
-            }
+            for (int s = 0; s < ST; ++s) o[qb] = P::mma(mine ? vop[kb][s] : op_t{}, P::op(st[kb], s), o[qb]);
         }
       }
       // normalise per head, then W_O into the residual
@@ -281,7 +300,7 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
       for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
         for (int s = 0; s < ST; ++s) xo[rb][ib][s] = P::op(x[rb][ib], s);
-#pragma unroll 1
+#pragma unroll 2
     for (int c = 0; c < MB; ++c) {
       float bias[16];
 #pragma unroll

@@ -3,7 +3,8 @@ where the stated ones cannot hold for the arithmetic itself.
 
 * ``bf16``: the same network as oracle.ansatz evaluated in FP64, with every
   matrix-product operand rounded to BF16 as the BF16 MFMA path does
-  (activations entering QKV, scores, P.V, W_O and the MLP, and the weights).
+  (activations entering QKV, q scaled by log2(e)/sqrt(dh), k, P.V, W_O and
+  the MLP, and the weights).
   Differentiated by autograd, the casts also round the gradients flowing back
   through those operands to BF16, which is what the BF16 backward does.
 * ``fp32``: the same network evaluated entirely in FP32 (torch on the CPU).
@@ -39,7 +40,9 @@ def _z(p, arch, bl, br, R):
         q = (xr @ R(p[f"l{l}_wq"])).reshape(B, N, H, dh).transpose(1, 2)
         k = (xr @ R(p[f"l{l}_wk"])).reshape(B, N, H, dh).transpose(1, 2)
         v = (xr @ R(p[f"l{l}_wv"])).reshape(B, N, H, dh).transpose(1, 2)
-        s = (R(q) @ R(k).transpose(-1, -2)) / math.sqrt(dh)
+        # the kernels fold the softmax scale log2(e)/sqrt(dh) into q before rounding it
+        c = math.log2(math.e) / math.sqrt(dh)
+        s = (R(q * c) @ R(k).transpose(-1, -2)) / math.log2(math.e)
         e = torch.exp(s - s.max(-1, keepdim=True).values)
         o = (R(e) @ R(v)) / e.sum(-1, keepdim=True)
         x = x + R(o.transpose(1, 2).reshape(B, N, d)) @ R(p[f"l{l}_wo"])
