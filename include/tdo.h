@@ -9,7 +9,8 @@
  *   word 0 = alpha, word 1 = beta (the row and column labels of
  *   rho(alpha, beta) in the vectorisation |rho>> = sum rho_ab |a>|b>, App. A).
  *   Bit i is site i; bit value 0 = spin up (sigma^z = +1), 1 = spin down.
- *   Bits at positions >= n must be zero (TDO_EINVAL otherwise).
+ *   Bits at positions >= n must be zero; configurations live in device
+ *   memory and are not checked (results are unspecified otherwise).
  * - Complex numbers are two consecutive floats (re, im) or doubles.
  * - Every pointer argument named as device memory must point to memory on the
  *   context's device; host pointers are marked "host".  The caller owns and
@@ -150,6 +151,29 @@ int32_t tdo_loss_grad(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *param
                       const tdo_model_t *model, const uint64_t *cfg, int64_t B,
                       const double *weights, tdo_prec_t prec, int32_t grad_mode, double *loss,
                       double *grad, float *lloc_out, hipStream_t stream);
+
+/* Cost and gradient (as tdo_loss_grad with lloc_out = NULL) of n_problems
+ * independent problems sharing one architecture (App. C, Eq. lossnetk, for each
+ * problem): problem p has the model models[p] (its own chain length and
+ * couplings), parameters params[p] (device float [P]), samples cfg[p] (device
+ * uint64 [B[p]][2]) and weights weights[p] (device double [B[p]], or NULL; the
+ * array itself may be NULL), and writes loss[p] (device double [n_problems])
+ * and grad[p] (device double [P]).  models, params, cfg, B, weights and grad are
+ * host arrays of n_problems entries.  The problems run in order on the stream.
+ * The first call with given arguments runs eagerly: it sizes the workspace for
+ * the largest problem and autotunes the forward launch shape for every
+ * distinct chain length.  The second identical call on a stream other than
+ * the legacy default stream records the whole launch sequence into a HIP
+ * graph, and every later identical call replays it (inputs are read when the
+ * graph runs, so their contents may change between calls; their addresses may
+ * not).  A call of any entry point that grows the context's workspace
+ * invalidates the recording, which is then made again.  Every problem is
+ * validated before anything is launched. */
+int32_t tdo_loss_grad_batched(tdo_ctx_t *ctx, const tdo_arch_t *arch, int32_t n_problems,
+                              const tdo_model_t *models, const float *const *params,
+                              const uint64_t *const *cfg, const int64_t *B,
+                              const double *const *weights, tdo_prec_t prec, int32_t grad_mode,
+                              double *loss, double *const *grad, hipStream_t stream);
 
 /* Metropolis-Hastings on P ~ |rho|^2 (App. C, "Efficient Sampling Strategy"),
  * `chains` independent chains, `sweeps` sweeps of 2n proposals each.  Proposal

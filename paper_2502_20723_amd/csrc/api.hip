@@ -24,6 +24,19 @@ int32_t set_error(int32_t code, const char* fmt, ...) {
 }
 void clear_error() { g_err.clear(); }
 
+int32_t allow_full_lds(const void* kern) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, int>> done;
+  int dev = 0;
+  TDO_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  for (const auto& d : done)
+    if (d.first == kern && d.second == dev) return TDO_OK;
+  TDO_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  done.emplace_back(kern, dev);
+  return TDO_OK;
+}
+
 // ---------------------------------------------------------------- profiler
 hipEvent_t Profiler::get() {
   if (!pool.empty()) {
@@ -54,7 +67,7 @@ void Profiler::destroy() {
 }
 
 ProfScope::ProfScope(Profiler* p_, const char* name_, hipStream_t st_) : p(p_), name(name_), st(st_) {
-  if (p && p->enabled) {
+  if (p && p->enabled && !p->suspended) {
     start = p->get();
     if (start) (void)hipEventRecord(start, st);
   }
@@ -113,6 +126,10 @@ int32_t net_plan(const Context* c, const tdo_arch_t* arch, int n, bool bf16, Net
   np->elem = bf16 ? 2 : 4;
   np->num_cus = c->num_cus;
   np->prof = const_cast<Profiler*>(&c->prof);
+  np->fwd_wg_per_cu = 1;
+  const uint64_t key = tune_key(*np);
+  for (const TuneEntry& e : c->tune)
+    if (e.key == key) np->fwd_wg_per_cu = e.fwd_wg_per_cu;
   return TDO_OK;
 }
 
@@ -150,7 +167,7 @@ int32_t run_forward(const NetPlan& np, const NetWeights& w, const uint64_t* ecfg
     a.first = l == 0;
     a.last = l == L - 1;
     a.masked = np.masked;
-    a.blocks_per_cu = 1;
+    a.blocks_per_cu = np.fwd_wg_per_cu;
     ProfScope ps(np.prof, "fwd_layer", st);
     TDO_TRY(launch_fwd_layer(a, np.bf16, np.D, np.DH, np.span, np.num_cus, st));
   }
@@ -216,6 +233,7 @@ int32_t tdo_ctx_destroy(tdo_ctx_t* ctx) {
   TDO_HIP(hipSetDevice(ctx->c.device));
   TDO_HIP(hipDeviceSynchronize());
   ctx->c.prof.destroy();
+  if (ctx->c.graph.exec) TDO_HIP(hipGraphExecDestroy(ctx->c.graph.exec));
   if (ctx->c.ws) TDO_HIP(hipFree(ctx->c.ws));
   delete ctx;
   return TDO_OK;

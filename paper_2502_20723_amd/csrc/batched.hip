@@ -1,0 +1,171 @@
+// Cost and gradient of many independent problems in one call: every problem
+// has its own chain length, Lindbladian, parameters and samples, all share one
+// architecture.  The problems are dispatched on one stream in order; the call
+// records its whole launch sequence into a HIP graph the second time it is made
+// with the same arguments, and replays the graph on every later identical call,
+// so that the per-launch cost of the hundreds of small kernels of many problems
+// is paid once.
+//
+// The first (eager) call also autotunes, per distinct (chain length,
+// precision, width, head width, depth, MLP width), the number of workgroups per
+// CU of the forward layer kernel: each candidate runs the full forward over the
+// problem's first chunk of configurations and the fastest is kept in the context.
+#include <algorithm>
+#include <cstring>
+
+#include "common.h"
+#include "lindblad.h"
+#include "netapi.h"
+#include "train.h"
+
+namespace tdo {
+
+namespace {
+
+template <class T>
+void put(std::vector<uint8_t>& k, const T& v) {
+  const uint8_t* p = reinterpret_cast<const uint8_t*>(&v);
+  k.insert(k.end(), p, p + sizeof(T));
+}
+
+// Candidates and measurement of the forward grid.
+int32_t tune_forward(Context& c, NetPlan& np, const float* params, const uint64_t* cfg, int64_t E, hipStream_t st) {
+  const uint64_t key = tune_key(np);
+  for (const TuneEntry& e : c.tune)
+    if (e.key == key) {
+      np.fwd_wg_per_cu = e.fwd_wg_per_cu;
+      return TDO_OK;
+    }
+  // workspace: weights, two residual buffers and z for the E configurations (a prefix of the samples)
+  Arena ar;
+  size_t woff[4];
+  carve_weights(np, ar, woff);
+  const int64_t nblk = blocks_for(np, E);
+  const size_t oxa = ar.take<float>((size_t)nblk * 32 * np.D);
+  const size_t oxb = ar.take<float>((size_t)nblk * 32 * np.D);
+  const size_t oz = ar.take<float>((size_t)E * 4);
+  if (ar.used > c.ws_size) return TDO_OK;  // keep the default rather than grow the workspace for tuning
+  NetWeights w = weights_at(c.ws, woff);
+  TDO_TRY(pack_weights(np, params, &w, st));
+  hipEvent_t ev[2];
+  TDO_HIP(hipEventCreate(&ev[0]));
+  TDO_HIP(hipEventCreate(&ev[1]));
+  const int cand[3] = {1, 2, 4};
+  int best = 1;
+  float best_ms = 0.f;
+  int32_t rc = TDO_OK;
+  for (int rep = 0; rep < 2 && rc == TDO_OK; ++rep)  // first round warms caches and code objects
+    for (int ci = 0; ci < 3 && rc == TDO_OK; ++ci) {
+      np.fwd_wg_per_cu = cand[ci];
+      if (hipEventRecord(ev[0], st) != hipSuccess) { rc = set_error(TDO_EHIP, "hipEventRecord failed"); break; }
+      rc = run_forward(np, w, cfg, E, nullptr, at<float>(c.ws, oxa), at<float>(c.ws, oxb), nullptr, at<float>(c.ws, oz), st);
+      if (rc != TDO_OK) break;
+      if (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) {
+        rc = set_error(TDO_EHIP, "event timing of the forward candidates failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (rep == 1 && (ci == 0 || ms < best_ms)) {
+        best_ms = ms;
+        best = cand[ci];
+      }
+    }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  TDO_TRY(rc);
+  np.fwd_wg_per_cu = best;
+  c.tune.push_back({key, best});
+  return TDO_OK;
+}
+
+}  // namespace
+
+}  // namespace tdo
+
+using namespace tdo;
+
+extern "C" int32_t tdo_loss_grad_batched(tdo_ctx_t* ctx, const tdo_arch_t* arch, int32_t n_problems,
+                                         const tdo_model_t* models, const float* const* params,
+                                         const uint64_t* const* cfg, const int64_t* B, const double* const* weights,
+                                         tdo_prec_t prec, int32_t grad_mode, double* loss, double* const* grad,
+                                         hipStream_t stream) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  TDO_CHECK(n_problems >= 0, TDO_EINVAL, "n_problems=%d < 0", n_problems);
+  if (n_problems == 0) return TDO_OK;
+  TDO_CHECK(arch && models && params && cfg && B && loss && grad, TDO_EINVAL, "NULL argument");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  Context& c = ctx->c;
+  // validate every problem and size the workspace for the largest before any launch
+  std::vector<ModelDev> m(n_problems);
+  std::vector<NetPlan> np(n_problems);
+  std::vector<TrainWs> t(n_problems);
+  for (int32_t p = 0; p < n_problems; ++p) {
+    const int32_t s = loss_grad_check(c, arch, &models[p], B[p], prec, grad_mode, &m[p], &np[p], &t[p]);
+    if (s != TDO_OK) return set_error(s, "problem %d: %s", p, tdo_last_error());
+    TDO_CHECK(params[p] && cfg[p] && grad[p], TDO_EINVAL, "problem %d: NULL buffer", p);
+  }
+  std::vector<uint8_t> key;
+  put(key, *arch);
+  put(key, n_problems);
+  put(key, prec);
+  put(key, grad_mode);
+  put(key, loss);
+  put(key, stream);
+  put(key, weights != nullptr);
+  for (int32_t p = 0; p < n_problems; ++p) {
+    put(key, models[p]);
+    put(key, params[p]);
+    put(key, cfg[p]);
+    put(key, B[p]);
+    put(key, grad[p]);
+    put(key, weights ? weights[p] : nullptr);
+  }
+  GraphCache& gc = c.graph;
+  auto run_all = [&]() -> int32_t {
+    for (int32_t p = 0; p < n_problems; ++p)
+      TDO_TRY(loss_grad_run(c, np[p], m[p], t[p], params[p], cfg[p], B[p], weights ? weights[p] : nullptr, grad_mode,
+                            loss + p, grad[p], nullptr, stream));
+    return TDO_OK;
+  };
+  // 1. replay a recording of exactly this call
+  if (gc.exec && key == gc.key && gc.ws == c.ws) {
+    TDO_HIP(hipGraphLaunch(gc.exec, stream));
+    return TDO_OK;
+  }
+  // 2. second identical call: record and replay (never on the legacy default stream)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  TDO_HIP(hipStreamIsCapturing(stream, &cap));
+  if (stream != nullptr && cap == hipStreamCaptureStatusNone && key == gc.seen_key && gc.seen_ws == c.ws) {
+    TDO_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    c.prof.suspended = true;
+    const int32_t rc = run_all();
+    c.prof.suspended = false;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(stream, &g);
+    TDO_TRY(rc);
+    TDO_CHECK(ec == hipSuccess && g, TDO_EHIP, "recording the batched launch sequence failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    TDO_CHECK(ei == hipSuccess, TDO_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    gc.exec = exec;
+    gc.key = key;
+    gc.ws = c.ws;
+    TDO_HIP(hipGraphLaunch(gc.exec, stream));
+    return TDO_OK;
+  }
+  // 3. eager call: autotune the forward grid per distinct shape, then run
+  if (cap == hipStreamCaptureStatusNone) {
+    for (int32_t p = 0; p < n_problems; ++p) {
+      const int64_t E = std::min<int64_t>(B[p], t[p].chunk);
+      TDO_TRY(tune_forward(c, np[p], params[p], cfg[p], E, stream));
+    }
+  }
+  TDO_TRY(run_all());
+  gc.seen_key = key;
+  gc.seen_ws = c.ws;
+  return TDO_OK;
+}

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +44,7 @@ void clear_error();
 // from a pool owned by the context and are read (and returned) on request.
 struct Profiler {
   bool enabled = false;
+  bool suspended = false;  // set while a launch sequence is recorded into a graph
   struct Rec {
     const char* name;
     hipEvent_t start, stop;
@@ -63,6 +65,28 @@ struct ProfScope {
   ~ProfScope();
 };
 
+// ---------------------------------------------------------------- graphs and tuning
+// Recorded launch sequence of the batched loss/gradient: the arguments it was
+// recorded for (including the workspace base), and the instantiated graph.
+struct GraphCache {
+  std::vector<uint8_t> seen_key, key;  // arguments of the last eager call / of the recording
+  void* seen_ws = nullptr;
+  void* ws = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+// Autotuned launch shapes: workgroups per CU of the forward layer kernel, per
+// (chain length, precision, padded width, head width).
+struct TuneEntry {
+  uint64_t key;
+  int fwd_wg_per_cu;
+};
+
+// Allow a kernel the whole 160 KB LDS of a CU, once per kernel and device per
+// process (a host-side attribute, so later launches, also while a stream is
+// being recorded into a graph, need no further runtime call).
+int32_t allow_full_lds(const void* kern);
+
 // ---------------------------------------------------------------- context
 struct Context {
   int device = 0;
@@ -71,6 +95,8 @@ struct Context {
   void* ws = nullptr;
   size_t ws_size = 0;
   Profiler prof;
+  GraphCache graph;
+  std::vector<TuneEntry> tune;
 };
 
 // Grow the context workspace to at least `bytes` (<= budget).

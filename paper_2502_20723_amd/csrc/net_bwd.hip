@@ -425,81 +425,122 @@ __global__ void __launch_bounds__(256) k_bwd_attn(BwdArgs a) {
 }
 
 // ------------------------------------------------------------------ head and embedding
-// dW_head[f][k] += mean over the rows of x_L [f] * dF_k, db_head[k] += dF_k (FP64 atomics).
+// dW_head[f][k] += sum over configuration-passes of (mean over its rows of x_L[f]) dF_k,
+// db_head[k] += dF_k.  One wave per block of the saved x_L (lane -> row, values ->
+// features): each lane adds x_L[row][f] dF_k / n for its row into FP64
+// accumulators; the lanes of a feature are summed once per launch and added to
+// the FP64 gradient atomically.
 template <class P, int D>
-__global__ void k_bwd_head(const void* __restrict__ save_last, const float* __restrict__ seeds, const int64_t* E_dev,
-                           int64_t E_host, int n, int cpb, int span, int d_real, double* __restrict__ gw,
-                           double* __restrict__ gb) {
+__global__ void __launch_bounds__(256) k_bwd_head(const void* __restrict__ save_last, const float* __restrict__ seeds,
+                                                  const int64_t* E_dev, int64_t E_host, int n, int cpb, int span,
+                                                  int d_real, double* __restrict__ gw, double* __restrict__ gb) {
   using save_t = typename P::save_t;
   constexpr int NB = D / 32;
   const int64_t E = E_dev ? *E_dev : E_host;
+  const RowMap rm{n, cpb, span != 0};
+  const int64_t nblk = span ? 4 * E : 2 * ((E + cpb - 1) / cpb);
+  const int lane = threadIdx.x & 63, h = lane >> 5, lr = lane & 31, wave = threadIdx.x >> 6;
   const save_t* xs = reinterpret_cast<const save_t*>(save_last);
-  // thread -> feature f (< D); grid-stride over configuration-passes
-  const int f = threadIdx.x;
-  double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
-  const int ob = f / 32, fi = f % 32, hf = (fi >> 2) & 1, rf = 4 * (fi >> 3) + (fi & 3);
-  for (int64_t cp = blockIdx.x; cp < 2 * E; cp += gridDim.x) {
-    const int64_t e = cp >> 1;
-    const int pass = (int)(cp & 1);
-    const float s0 = seeds[cp * 2], s1 = seeds[cp * 2 + 1];
-    float hsum = 0.f;
-    for (int i = 0; i < n; ++i) {
-      int64_t g;
-      int row;
-      if (span) { g = (2 * e + pass) * 2 + (i >> 5); row = i & 31; }
-      else { g = 2 * (e / cpb) + pass; row = (int)(e % cpb) * n + i; }
-      hsum += (float)xs[((g * NB + ob) * 64 + row + 32 * hf) * 16 + rf];
+  const float inv_n = 1.0f / (float)n;
+  double a0[NB][16], a1[NB][16], c0 = 0.0, c1 = 0.0;
+#pragma unroll
+  for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a0[ob][r] = a1[ob][r] = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * 4 + wave; g < nblk; g += (int64_t)gridDim.x * 4) {
+    int64_t e; int pass, ric; bool valid;
+    rm.at(g, lr, E, e, pass, ric, valid);
+    if (!valid) continue;
+    const float s0 = seeds[(e * 2 + pass) * 2] * inv_n, s1 = seeds[(e * 2 + pass) * 2 + 1] * inv_n;
+    if (h == 0) { c0 += s0; c1 += s1; }
+#pragma unroll
+    for (int ob = 0; ob < NB; ++ob) {
+      f32x16 v;
+      load_tile(xs + ((g * NB + ob) * 64 + lane) * 16, v);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        a0[ob][r] += (double)(v[r] * s0);
+        a1[ob][r] += (double)(v[r] * s1);
+      }
     }
-    const double hm = (double)hsum / n;
-    a0 += hm * s0;
-    a1 += hm * s1;
-    if (f == 0) { c0 += s0; c1 += s1; }
   }
-  if (f < d_real) {
-    atomicAdd(gw + 2 * f, a0);
-    atomicAdd(gw + 2 * f + 1, a1);
-  }
-  if (f == 0) {
+  // sum over the 32 rows (lanes of one half), then one atomic per feature and workgroup wave
+#pragma unroll
+  for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double u0 = a0[ob][r], u1 = a1[ob][r];
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) { u0 += __shfl_xor(u0, o, 64); u1 += __shfl_xor(u1, o, 64); }
+      const int f = 32 * ob + tile_idx(r, h);
+      if (lr == 0 && f < d_real) {
+        atomicAdd(gw + 2 * f, u0);
+        atomicAdd(gw + 2 * f + 1, u1);
+      }
+    }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) { c0 += __shfl_xor(c0, o, 64); c1 += __shfl_xor(c1, o, 64); }
+  if (lane == 0) {
     atomicAdd(gb, c0);
     atomicAdd(gb + 1, c1);
   }
 }
 
-// dT[code][f] += dx_0 over rows (LDS-privatised), then per-workgroup partials.
+// dT[code][f] += sum over rows with that window code of dx_0[row][f], as an MFMA
+// contraction over the rows of each block: C[f][code] = sum_row dx_0[row][f] onehot[row][code]
+// (FP32 operands, exact one-hot), accumulated in registers by every wave over its
+// blocks and written to the wave's partial slot [64][D] once per launch.
 template <int D>
-__global__ void __launch_bounds__(256) k_embed_scatter(const float* __restrict__ dx0, const uint64_t* __restrict__ ecfg,
-                                                       const int64_t* E_dev, int64_t E_host, int n, int cpb, int span,
-                                                       float* __restrict__ partial) {
+__global__ void __launch_bounds__(256) k_embed_onehot(const float* __restrict__ dx0, const uint64_t* __restrict__ ecfg,
+                                                      const int64_t* E_dev, int64_t E_host, int n, int cpb, int span,
+                                                      float* __restrict__ partial) {
   constexpr int NB = D / 32;
-  __shared__ float dT[64 * D];
-  for (int i = threadIdx.x; i < 64 * D; i += blockDim.x) dT[i] = 0.f;
-  __syncthreads();
   const int64_t E = E_dev ? *E_dev : E_host;
   const RowMap rm{n, cpb, span != 0};
   const int64_t nblk = span ? 4 * E : 2 * ((E + cpb - 1) / cpb);
   const int lane = threadIdx.x & 63, h = lane >> 5, lr = lane & 31, wave = threadIdx.x >> 6;
+  f32x16 acc[NB][2];
+#pragma unroll
+  for (int ft = 0; ft < NB; ++ft) acc[ft][0] = acc[ft][1] = f32x16{};
   for (int64_t g = (int64_t)blockIdx.x * 4 + wave; g < nblk; g += (int64_t)gridDim.x * 4) {
+    // window code of this lane's row (-1 if the row is padding)
     int64_t e; int pass, ric; bool valid;
     rm.at(g, lr, E, e, pass, ric, valid);
-    if (!valid) continue;
-    const uint64_t al = ecfg[2 * e], be = ecfg[2 * e + 1];
-    const uint64_t c0 = pass ? be : al, c1 = pass ? al : be;
-    int code = 0;
-    for (int k = 0; k < 3; ++k) {
-      int s = ric + k;
-      s = s >= n ? s - n : s;
-      code += ((int)((c0 >> s) & 1ull) + 2 * (int)((c1 >> s) & 1ull)) << (2 * k);
+    int code = -1;
+    if (valid) {
+      const uint64_t al = ecfg[2 * e], be = ecfg[2 * e + 1];
+      const uint64_t c0 = pass ? be : al, c1 = pass ? al : be;
+      code = 0;
+      for (int k = 0; k < 3; ++k) {
+        int s = ric + k;
+        s = s >= n ? s - n : s;
+        code += ((int)((c0 >> s) & 1ull) + 2 * (int)((c1 >> s) & 1ull)) << (2 * k);
+      }
     }
 #pragma unroll
-    for (int ob = 0; ob < NB; ++ob) {
-      f32x16 v;
-      load_tile(dx0 + ((g * NB + ob) * 64 + lane) * 16, v);
+    for (int s = 0; s < 16; ++s) {
+      const int row = tile_idx(s, h);
+      const int rc = __shfl(code, row, 64);  // code of the row this k-step holds
 #pragma unroll
-      for (int r = 0; r < 16; ++r) atomicAdd(dT + code * D + 32 * ob + tile_idx(r, h), v[r]);
+      for (int ft = 0; ft < NB; ++ft) {
+        // dx_0[row][32 ft + lr] from the block-major layout
+        const int fi = lr, hf = (fi >> 2) & 1, rf = 4 * (fi >> 3) + (fi & 3);
+        const float a = dx0[((g * NB + ft) * 64 + row + 32 * hf) * 16 + rf];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const float b = (rc == 32 * ct + lr) ? 1.0f : 0.0f;
+          acc[ft][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[ft][ct], 0, 0, 0);
+        }
+      }
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 64 * D; i += blockDim.x) partial[(int64_t)blockIdx.x * 64 * D + i] = dT[i];
+  float* part = partial + ((int64_t)blockIdx.x * 4 + wave) * 64 * D;
+#pragma unroll
+  for (int ft = 0; ft < NB; ++ft)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) part[(32 * ct + lr) * D + 32 * ft + tile_idx(r, h)] = acc[ft][ct][r];
 }
 
 // Chain rule from the table gradient dT[64][D] (FP64) into the convolution
@@ -597,7 +638,7 @@ template <class P, int D>
 static int32_t mlp_t(const BwdArgs& a, int blocks, hipStream_t st) {
   const size_t lds = (size_t)(2 * D * a.M + a.M + D) * 4 + 4 * 32 * TS * 4;
   auto k = k_bwd_mlp<P, D>;
-  TDO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  TDO_TRY(allow_full_lds((const void*)k));
   hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
@@ -607,7 +648,7 @@ template <class P, int D, int DH, bool SPAN>
 static int32_t attn_t(const BwdArgs& a, int blocks, hipStream_t st) {
   const size_t lds = (size_t)4 * D * D * 4 + 4 * 32 * TS * 4;
   auto k = k_bwd_attn<P, D, DH, SPAN>;
-  TDO_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  TDO_TRY(allow_full_lds((const void*)k));
   hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, a);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
@@ -637,11 +678,11 @@ int32_t launch_bwd_attn(const BwdArgs& a, bool bf16, int D, int DH, int blocks, 
 int32_t launch_bwd_head(bool bf16, int D, const void* save_last, const float* seeds, const int64_t* E_dev,
                         int64_t E_host, int n, int cpb, int span, int d_real, double* gw, double* gb, hipStream_t st) {
   if (D == 32) {
-    if (bf16) hipLaunchKernelGGL((k_bwd_head<PBF16, 32>), dim3(1024), dim3(32), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
-    else hipLaunchKernelGGL((k_bwd_head<PF32, 32>), dim3(1024), dim3(32), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
+    if (bf16) hipLaunchKernelGGL((k_bwd_head<PBF16, 32>), dim3(1024), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
+    else hipLaunchKernelGGL((k_bwd_head<PF32, 32>), dim3(1024), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
   } else {
-    if (bf16) hipLaunchKernelGGL((k_bwd_head<PBF16, 64>), dim3(1024), dim3(64), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
-    else hipLaunchKernelGGL((k_bwd_head<PF32, 64>), dim3(1024), dim3(64), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
+    if (bf16) hipLaunchKernelGGL((k_bwd_head<PBF16, 64>), dim3(1024), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
+    else hipLaunchKernelGGL((k_bwd_head<PF32, 64>), dim3(1024), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
   }
   TDO_HIP(hipGetLastError());
   return TDO_OK;
@@ -649,8 +690,9 @@ int32_t launch_bwd_head(bool bf16, int D, const void* save_last, const float* se
 
 int32_t launch_embed_scatter(int D, const float* dx0, const uint64_t* ecfg, const int64_t* E_dev, int64_t E_host,
                              int n, int cpb, int span, float* partial, int blocks, hipStream_t st) {
-  if (D == 32) hipLaunchKernelGGL(k_embed_scatter<32>, dim3(blocks), dim3(256), 0, st, dx0, ecfg, E_dev, E_host, n, cpb, span, partial);
-  else hipLaunchKernelGGL(k_embed_scatter<64>, dim3(blocks), dim3(256), 0, st, dx0, ecfg, E_dev, E_host, n, cpb, span, partial);
+  // `blocks` workgroups of 4 waves; each wave writes one [64][D] partial (4 * blocks partials)
+  if (D == 32) hipLaunchKernelGGL(k_embed_onehot<32>, dim3(blocks), dim3(256), 0, st, dx0, ecfg, E_dev, E_host, n, cpb, span, partial);
+  else hipLaunchKernelGGL(k_embed_onehot<64>, dim3(blocks), dim3(256), 0, st, dx0, ecfg, E_dev, E_host, n, cpb, span, partial);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
 }

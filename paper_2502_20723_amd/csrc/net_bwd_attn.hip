@@ -319,7 +319,7 @@ bool bwd_attn_bf16_supported(int d, int D, int DH, bool span) { return d == 64 &
 int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t st) {
   const size_t lds = bwd_attn_bf16_lds();
   auto go = [&](auto kern) -> int32_t {
-    TDO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    TDO_TRY(allow_full_lds((const void*)kern));
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
     TDO_HIP(hipGetLastError());
     return TDO_OK;

@@ -403,7 +403,7 @@ static int32_t launch_layer_t(const FwdArgs& a, int num_cus, hipStream_t st) {
   const size_t wbytes = (P::KPL == 8) ? (size_t)(4 * D * D + 2 * D * a.M) * sizeof(typename P::elem_t) : 0;
   const size_t lds = wbytes + (size_t)(a.M + D) * 4 + (a.first ? 64 * D * 4 : 0) + 4 * 64 * sizeof(float2);
   auto kern = k_fwd_layer<P, D, DH, SPAN>;
-  TDO_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  TDO_TRY(allow_full_lds((const void*)kern));
   const int blocks = num_cus * a.blocks_per_cu;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
   TDO_HIP(hipGetLastError());

@@ -14,7 +14,13 @@ struct NetPlan {
   int D, DH, n, cpb, elem, num_cus;
   float score_scale;
   Profiler* prof;
+  int fwd_wg_per_cu;  // workgroups per CU of the forward layer kernel (autotuned, default 1)
 };
+
+inline uint64_t tune_key(const NetPlan& np) {
+  return (uint64_t)np.n | ((uint64_t)np.bf16 << 8) | ((uint64_t)np.D << 16) | ((uint64_t)np.DH << 24) |
+         ((uint64_t)np.pp.layers << 32) | ((uint64_t)np.pp.M << 40);
+}
 
 struct NetWeights {
   void* wpack;       // [L][layer_elems] forward fragments
@@ -32,6 +38,24 @@ struct Saves {
   void* last;         // output of the last layer
   size_t layer_bytes; // bytes of one layer's buffer
 };
+
+// Workspace plan shared by the loss/gradient and VJP drivers.
+struct TrainWs {
+  size_t woff[4], wback, gA, Lall, acc, lpart, mlp_acc, attn_acc, dT_acc, partial;
+  size_t cnt, off, etot, ecfg, ecoef, eowner, lr, z, dF, xa, xb, sx, smid, slast;
+  int64_t chunk, emax, nblk;
+  size_t layer_bytes;
+};
+
+struct ModelDev;
+int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, TrainWs* t);
+// Validation and workspace plan of one loss/gradient evaluation (grows the workspace).
+int32_t loss_grad_check(const Context& c, const tdo_arch_t* arch, const tdo_model_t* model, int64_t B, tdo_prec_t prec,
+                        int32_t grad_mode, ModelDev* m, NetPlan* np, TrainWs* t);
+// The launch sequence of one loss/gradient evaluation on a planned workspace.
+int32_t loss_grad_run(Context& c, const NetPlan& np, const ModelDev& m, const TrainWs& t, const float* params,
+                      const uint64_t* cfg, int64_t B, const double* weights, int32_t grad_mode, double* loss,
+                      double* grad, float* lloc_out, hipStream_t stream);
 
 int32_t net_plan(const Context* c, const tdo_arch_t* arch, int n, bool bf16, NetPlan* np);
 int64_t blocks_for(const NetPlan& np, int64_t E);

@@ -181,22 +181,19 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
   }
   TDO_TRY(launch_bwd_head(np.bf16, D, sv.last, dF, E_dev, E, np.n, np.cpb, np.span, pp.d, gt + pp.off_head_w,
                           gt + pp.off_head_b, st));
-  TDO_TRY(fill(bb.dT_acc, 64LL * D, 0.0, st));
+  // table gradient accumulated over every call of this entry point; the chain rule into the
+  // convolution parameters (linear in it) runs once at the end (finish_backward)
   TDO_TRY(launch_embed_scatter(D, bb.ga, ecfg, E_dev, E, np.n, np.cpb, np.span, bb.partial, bb.nparts, st));
-  TDO_TRY(launch_reduce_partials(bb.partial, bb.nparts, 64LL * D, bb.dT_acc, st));
-  TDO_TRY(launch_embed_params(params, bb.dT_acc, pp.d, D, gt, st));
+  TDO_TRY(launch_reduce_partials(bb.partial, 4 * bb.nparts, 64LL * D, bb.dT_acc, st));
   return TDO_OK;
 }
 
-// Workspace plan shared by the loss/gradient and VJP drivers.
-struct TrainWs {
-  size_t woff[4], wback, gA, Lall, acc, lpart, mlp_acc, attn_acc, dT_acc, partial;
-  size_t cnt, off, etot, ecfg, ecoef, eowner, lr, z, dF, xa, xb, sx, smid, slast;
-  int64_t chunk, emax, nblk;
-  size_t layer_bytes;
-};
+static int32_t finish_backward(const NetPlan& np, const BwdBufs& bb, const float* params, double* gt, hipStream_t st) {
+  return launch_embed_params(params, bb.dT_acc, np.pp.d, np.D, gt, st);
+}
 
-static int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, TrainWs* t) {
+
+int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, TrainWs* t) {
   const PackPlan& pp = np.pp;
   TDO_CHECK(bwd_mlp_lds(np.D, pp.M) <= 160 * 1024, TDO_EUNSUPPORTED,
             "backward of width %d with mlp %d exceeds the LDS of a workgroup", np.D, pp.M);
@@ -211,7 +208,7 @@ static int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int ns
   t->mlp_acc = ar.take<double>(mlen);
   t->attn_acc = ar.take<double>(4LL * np.D * np.D);
   t->dT_acc = ar.take<double>(64LL * np.D);
-  const int64_t maxlen = std::max<int64_t>(std::max<int64_t>(mlen, 4LL * np.D * np.D), 64LL * np.D);
+  const int64_t maxlen = std::max<int64_t>(std::max<int64_t>(mlen, 4LL * np.D * np.D), 4 * 64LL * np.D);
   t->partial = ar.take<float>((size_t)c.num_cus * maxlen);
   const size_t fixed = ar.used + 64 * 256;  // includes the per-sample L buffer
   const int save = np.bf16 ? 2 : 4;
@@ -270,6 +267,7 @@ extern "C" int32_t tdo_log_rho_vjp(tdo_ctx_t* ctx, const tdo_arch_t* arch, const
   TDO_TRY(pack_weights(np, params, &w, stream));
   TDO_TRY(launch_pack_backward(np.pp, params, np.bf16, at<char>(ws, t.wback), stream));
   TDO_TRY(fill(grad, np.pp.nparams, 0.0, stream));
+  TDO_TRY(fill(at<double>(ws, t.dT_acc), 64LL * np.D, 0.0, stream));
   BwdBufs bb{at<char>(ws, t.wback), at<float>(ws, t.xa), at<float>(ws, t.xb), at<float>(ws, t.partial), c.num_cus,
              at<double>(ws, t.mlp_acc), at<double>(ws, t.attn_acc), at<double>(ws, t.dT_acc)};
   Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes};
@@ -281,26 +279,26 @@ extern "C" int32_t tdo_log_rho_vjp(tdo_ctx_t* ctx, const tdo_arch_t* arch, const
     TDO_HIP(hipGetLastError());
     TDO_TRY(run_backward(np, w, bb, params, ec, E, nullptr, sv, at<float>(ws, t.dF), grad, stream));
   }
+  TDO_TRY(finish_backward(np, bb, params, grad, stream));
   return TDO_OK;
 }
 
-extern "C" int32_t tdo_loss_grad(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params, const tdo_model_t* model,
-                                 const uint64_t* cfg, int64_t B, const double* weights, tdo_prec_t prec,
-                                 int32_t grad_mode, double* loss, double* grad, float* lloc_out, hipStream_t stream) {
-  clear_error();
-  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+namespace tdo {
+
+int32_t loss_grad_check(const Context& c, const tdo_arch_t* arch, const tdo_model_t* model, int64_t B, tdo_prec_t prec,
+                        int32_t grad_mode, ModelDev* m, NetPlan* np, TrainWs* t) {
   TDO_CHECK(prec == TDO_FP32 || prec == TDO_BF16, TDO_EINVAL, "unknown precision %d", (int)prec);
   TDO_CHECK(grad_mode == 0 || grad_mode == 1, TDO_EINVAL, "grad_mode %d not 0 (B) or 1 (A)", grad_mode);
-  ModelDev m;
-  TDO_TRY(make_model(model, &m));
-  NetPlan np;
-  TDO_TRY(net_plan(&ctx->c, arch, model->n, prec == TDO_BF16, &np));
+  TDO_CHECK(model != nullptr, TDO_EINVAL, "model is NULL");
+  TDO_TRY(make_model(model, m));
+  TDO_TRY(net_plan(&c, arch, model->n, prec == TDO_BF16, np));
   TDO_CHECK(B >= 1, TDO_EINVAL, "B=%lld < 1", (long long)B);
-  TDO_CHECK(params && cfg && loss && grad, TDO_EINVAL, "NULL buffer");
-  TDO_HIP(hipSetDevice(ctx->c.device));
-  Context& c = ctx->c;
-  TrainWs t;
-  TDO_TRY(plan_train(c, np, B, m.nslots, &t));
+  return plan_train(c, *np, B, m->nslots, t);
+}
+
+int32_t loss_grad_run(Context& c, const NetPlan& np, const ModelDev& m, const TrainWs& t, const float* params,
+                      const uint64_t* cfg, int64_t B, const double* weights, int32_t grad_mode, double* loss,
+                      double* grad, float* lloc_out, hipStream_t stream) {
   void* ws = c.ws;
   NetWeights w = weights_at(ws, t.woff);
   TDO_TRY(pack_weights(np, params, &w, stream));
@@ -310,6 +308,7 @@ extern "C" int32_t tdo_loss_grad(tdo_ctx_t* ctx, const tdo_arch_t* arch, const f
   double* acc = at<double>(ws, t.acc);
   float* Lall = lloc_out ? lloc_out : at<float>(ws, t.Lall);
   TDO_TRY(fill(gA, P, 0.0, stream));
+  TDO_TRY(fill(at<double>(ws, t.dT_acc), 64LL * np.D, 0.0, stream));
   TDO_TRY(fill(acc, 2, 0.0, stream));
   BwdBufs bb{at<char>(ws, t.wback), at<float>(ws, t.xa), at<float>(ws, t.xb), at<float>(ws, t.partial), c.num_cus,
              at<double>(ws, t.mlp_acc), at<double>(ws, t.attn_acc), at<double>(ws, t.dT_acc)};
@@ -342,7 +341,24 @@ extern "C" int32_t tdo_loss_grad(tdo_ctx_t* ctx, const tdo_arch_t* arch, const f
       TDO_TRY(run_backward(np, w, bb, params, ec, Bc, nullptr, sv, at<float>(ws, t.dF), gA, stream));
     }
   }
+  TDO_TRY(finish_backward(np, bb, params, gA, stream));
   hipLaunchKernelGGL(k_finalize, dim3(256), dim3(256), 0, stream, acc, gA, P, loss, grad);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
+}
+
+}  // namespace tdo
+
+extern "C" int32_t tdo_loss_grad(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params, const tdo_model_t* model,
+                                 const uint64_t* cfg, int64_t B, const double* weights, tdo_prec_t prec,
+                                 int32_t grad_mode, double* loss, double* grad, float* lloc_out, hipStream_t stream) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  ModelDev m;
+  NetPlan np;
+  TrainWs t;
+  TDO_TRY(loss_grad_check(ctx->c, arch, model, B, prec, grad_mode, &m, &np, &t));
+  TDO_CHECK(params && cfg && loss && grad, TDO_EINVAL, "NULL buffer");
+  return loss_grad_run(ctx->c, np, m, t, params, cfg, B, weights, grad_mode, loss, grad, lloc_out, stream);
 }

@@ -21,7 +21,7 @@ PREC = {"fp32": TDO_FP32, "bf16": TDO_BF16}
 # The entry points declared in include/tdo.h.
 EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_error", "tdo_profile",
            "tdo_profile_read", "tdo_connected", "tdo_local_lindbladian", "tdo_log_rho", "tdo_log_rho_vjp",
-           "tdo_loss_grad", "tdo_sample")
+           "tdo_loss_grad", "tdo_loss_grad_batched", "tdo_sample")
 
 
 class ArchT(ctypes.Structure):
@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
         L.tdo_log_rho_vjp.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp, vp]
         L.tdo_loss_grad.argtypes = [vp, ctypes.POINTER(ArchT), vp, ctypes.POINTER(ModelT), vp, i64, vp, i32, i32,
                                     vp, vp, vp, vp]
+        L.tdo_loss_grad_batched.argtypes = [vp, ctypes.POINTER(ArchT), i32, ctypes.POINTER(ModelT), vp, vp, vp, vp, i32,
+                                            i32, vp, vp, vp]
         L.tdo_sample.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, i64, vp, vp, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_uint64), i32, ctypes.c_float, i32, vp, vp]
         for name in EXPORTS:
@@ -205,6 +207,38 @@ class Ctx:
                                    _ptr(cfg), B, _ptr(weights), PREC[prec], {"B": 0, "A": 1}[mode], _ptr(loss),
                                    _ptr(grad), _ptr(lloc), _stream()))
         return loss, grad, lloc
+
+    def loss_grad_batched(self, arch: dict, params: list, models: list, cfgs: list, weights=None, prec="fp32",
+                          mode="B", out=None):
+        """Loss and gradient of several problems in one call.  out = (loss [n] float64
+        tensor, list of n float64 [P] tensors) reuses the output buffers, which lets a
+        repeated identical call replay its recorded graph."""
+        k = len(params)
+        if not (len(models) == len(cfgs) == k) or (weights is not None and len(weights) != k):
+            raise ValueError("params, models, cfgs (and weights) must have one entry per problem")
+        P = num_params(arch)
+        for i in range(k):
+            _dev(params[i], torch.float32, (P,), f"params[{i}]")
+            _dev(cfgs[i], torch.uint64, (cfgs[i].shape[0], 2), f"cfg[{i}]")
+            if weights is not None and weights[i] is not None:
+                _dev(weights[i], torch.float64, (cfgs[i].shape[0],), f"weights[{i}]")
+        dev = cfgs[0].device if k else torch.device("cuda")
+        if out is None:
+            loss = torch.empty((k,), dtype=torch.float64, device=dev)
+            grads = [torch.empty((P,), dtype=torch.float64, device=dev) for _ in range(k)]
+        else:
+            loss, grads = out
+            _dev(loss, torch.float64, (k,), "loss")
+            for i in range(k):
+                _dev(grads[i], torch.float64, (P,), f"grad[{i}]")
+        vpa = ctypes.c_void_p * max(k, 1)
+        mt = (ModelT * max(k, 1))(*[model_t(m) for m in models])
+        bt = (ctypes.c_int64 * max(k, 1))(*[int(c.shape[0]) for c in cfgs])
+        wt = None if weights is None else vpa(*[(w.data_ptr() if w is not None else None) for w in weights])
+        _check(lib().tdo_loss_grad_batched(self.h, ctypes.byref(arch_t(arch)), k, mt, vpa(*[p.data_ptr() for p in params]),
+                                           vpa(*[c.data_ptr() for c in cfgs]), bt, wt, PREC[prec], {"B": 0, "A": 1}[mode],
+                                           _ptr(loss), vpa(*[g.data_ptr() for g in grads]), _stream()))
+        return loss, grads
 
     def sample(self, arch: dict, params, n: int, state, state_lr, seed: int, counter: int, sweeps: int,
                p_pair=0.5, prec="fp32"):
