@@ -37,8 +37,8 @@ KERNELS = ("fwd_layer", "bwd_mlp", "bwd_attn")
 # Source files whose change invalidates a recorded HBM-traffic measurement.
 KERNEL_SOURCES = {
     "fwd_layer": ("net_fwd.hip", "net.h", "netapi.h"),
-    "bwd_mlp": ("net_bwd.hip", "net.h", "netapi.h"),
-    "bwd_attn": ("net_bwd.hip", "net.h", "netapi.h"),
+    "bwd_mlp": ("net_bwd_mlp.hip", "net.h", "netapi.h"),
+    "bwd_attn": ("net_bwd_attn.hip", "net.h", "netapi.h"),
 }
 
 
@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--workspace-gib", type=float, default=48.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the loss check against the oracle")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-workload and sampler measurements (BF16, reported beside the headline)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one elementwise copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -202,6 +204,11 @@ def main():
             loss_err[prec] = abs(float(lg[0]) - F_ref) / abs(F_ref)
         log(f"bench: loss rel. error vs FP64 oracle on 16 sampled rows: {loss_err}")
 
+    extras = None
+    if not args.no_extras:
+        extras = {"batched_uneven": bench_batched(ctx, tdo, synth, args.steps),
+                  "sampler": bench_sampler(ctx, arch, params, n, synth)}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(arch, model, params_np, cfg_np)
@@ -229,9 +236,71 @@ def main():
         "per_precision": results,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def evaluated_configs(ctx, model, cfg):
+    """Configurations evaluated for these samples: each sample plus its nonzero
+    off-diagonal Lindbladian entries."""
+    conn, _, ncon = ctx.connected(model, cfg)
+    diag = (conn[:, 0, 0] == cfg[:, 0]) & (conn[:, 0, 1] == cfg[:, 1])
+    return int(ncon.sum().item()) + int((~diag).sum().item())
+
+
+def bench_batched(ctx, tdo, synth, steps):
+    """64 problems (n in [8, 40], half Ising half XYZ, own parameters), 2048 samples
+    each, BF16, mode B, one tdo_loss_grad_batched call per step: eager call, recording
+    call, then `steps` timed graph replays on a side stream."""
+    import torch
+    wl = synth.WORKLOADS["batched_uneven"]
+    arch = wl["arch"]
+    models = synth.uneven_problems(wl["problems"], wl["seed"])
+    params = [torch.from_numpy(synth.params(arch, wl["seed"] + 7 * i, "init")).cuda() for i in range(len(models))]
+    cfgs = [torch.from_numpy(synth.configs(m["n"], wl["B"], wl["seed"] + 11 * i)).cuda() for i, m in enumerate(models)]
+    E = sum(evaluated_configs(ctx, m, c) for m, c in zip(models, cfgs))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        P = tdo.num_params(arch)
+        out = (torch.empty(len(models), dtype=torch.float64, device="cuda"),
+               [torch.empty(P, dtype=torch.float64, device="cuda") for _ in models])
+        for _ in range(2):  # eager (sizes, autotunes), then recorded
+            ctx.loss_grad_batched(arch, params, models, cfgs, None, "bf16", "B", out=out)
+        s.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            ctx.loss_grad_batched(arch, params, models, cfgs, None, "bf16", "B", out=out)
+        e1.record(s)
+        s.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    log(f"bench: batched workload {len(models)} problems, {E} configurations: {ms:.1f} ms/step, "
+        f"{E / ms * 1e3 / 1e6:.3f} M configs/s (bf16, graph replay)")
+    return {"value": E / (ms / 1e3), "unit": "configs/s", "ms_per_step": ms, "configs_per_step": E,
+            "problems": len(models), "B": wl["B"], "dtype": "bf16", "steps": steps}
+
+
+def bench_sampler(ctx, arch, params, n, synth):
+    """Metropolis sampling with the n = 32 network: 65536 chains, one sweep (2n
+    proposals each) after one untimed sweep, BF16."""
+    import torch
+    C = 65536
+    state = torch.from_numpy(synth.configs(n, C, 4000)).cuda()
+    lr = ctx.log_rho(arch, params, n, state, "bf16")
+    _, ctr = ctx.sample(arch, params, n, state, lr, 1, 0, 1, 0.5, "bf16")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.sample(arch, params, n, state, lr, 1, ctr, 1, 0.5, "bf16")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    props = C * 2 * n
+    log(f"bench: sampler {C} chains x {2 * n} proposals in {ms:.1f} ms: {props / ms * 1e3 / 1e6:.2f} M proposals/s")
+    return {"value": props / (ms / 1e3), "unit": "proposals/s", "chains": C, "sweeps": 1, "ms": ms, "dtype": "bf16"}
 
 
 def cpu_baseline(arch, model, params_np, cfg_np):

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace tdo {
@@ -49,6 +51,29 @@ struct PBF16 {
     for (int t = 0; t < 8; ++t) o[t] = (__bf16)v[8 * s + t];
     return o;
   }
+  // Score operand of one head: its DH features of a 32-feature result tile
+  // (values [DH/2*j, DH/2*j + DH/2) of each lane), packed once and reused.
+  template <int DH>
+  struct SOp {
+    typename std::conditional<DH == 8, s16x4, bf16x8>::type v;
+  };
+  template <int DH>
+  __device__ static __forceinline__ SOp<DH> pack_head(const f32x16& x, int j) {
+    SOp<DH> o;
+    if constexpr (DH == 8) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) o.v[t] = bf16_bits(x[4 * j + t]);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) o.v[t] = (__bf16)x[8 * j + t];
+    }
+    return o;
+  }
+  template <int DH>
+  __device__ static __forceinline__ f32x16 scores_packed(const SOp<DH>& a, const SOp<DH>& b, f32x16 c) {
+    if constexpr (DH == 8) return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a.v, b.v, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, b.v, c, 0, 0, 0);
+  }
   // Attention scores over DH features of head j (values [DH/2*j, DH/2*j + DH/2)).
   template <int DH>
   __device__ static __forceinline__ f32x16 scores(const f32x16& kv, const f32x16& qv, int j, f32x16 c) {
@@ -78,6 +103,23 @@ struct PF32 {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
   }
   __device__ static __forceinline__ op_t op(const f32x16& v, int s) { return v[s]; }
+  template <int DH>
+  struct SOp {
+    float v[DH / 2];
+  };
+  template <int DH>
+  __device__ static __forceinline__ SOp<DH> pack_head(const f32x16& x, int j) {
+    SOp<DH> o;
+#pragma unroll
+    for (int t = 0; t < DH / 2; ++t) o.v[t] = x[(DH / 2) * j + t];
+    return o;
+  }
+  template <int DH>
+  __device__ static __forceinline__ f32x16 scores_packed(const SOp<DH>& a, const SOp<DH>& b, f32x16 c) {
+#pragma unroll
+    for (int t = 0; t < DH / 2; ++t) c = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[t], b.v[t], c, 0, 0, 0);
+    return c;
+  }
   template <int DH>
   __device__ static __forceinline__ f32x16 scores(const f32x16& kv, const f32x16& qv, int j, f32x16 c) {
     constexpr int PER = DH / 2;

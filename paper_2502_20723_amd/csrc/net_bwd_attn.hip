@@ -176,6 +176,15 @@ __global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
       for (int s = 0; s < ST; ++s) { QFb[s] = op8(QF, s); KFb[s] = op8(KF, s); VFb[s] = op8(VF, s); OFb[s] = op8(OF, s); }
 #pragma unroll
       for (int r = 0; r < 16; ++r) QR[r] *= sc;
+      using sop = PBF16::SOp<DH>;
+      sop QRp[HPB], KRp[HPB], VRp[HPB], ORp[HPB];  // per-head score operands, packed once
+#pragma unroll
+      for (int j = 0; j < HPB; ++j) {
+        QRp[j] = PBF16::pack_head<DH>(QR, j);
+        KRp[j] = PBF16::pack_head<DH>(KR, j);
+        VRp[j] = PBF16::pack_head<DH>(VR, j);
+        ORp[j] = PBF16::pack_head<DH>(OR, j);
+      }
       // key-major transposes of P and dS go through the part of this block's O and dV staging
       // that head block hb fills only after its heads are done
       __bf16* TP = S + SO * MAT + 32 * hb * FS;
@@ -185,14 +194,16 @@ __global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
       for (int j = 0; j < HPB; ++j) {
         const bool mine = (lr / DH) == j;
         // query-major tiles: lane -> query lr, values -> keys tile_idx(r, h)
-        f32x16 sq = PBF16::scores<DH>(KR, QR, j, f32x16{});
-        f32x16 dpq = PBF16::scores<DH>(VR, OR, j, f32x16{});
+        f32x16 sq = PBF16::scores_packed<DH>(KRp[j], QRp[j], f32x16{});
+        f32x16 dpq = PBF16::scores_packed<DH>(VRp[j], ORp[j], f32x16{});
+        if (masked) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            if (!((okbits >> r) & 1u)) sq[r] = -INFINITY;
+        }
         float m = -INFINITY;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          if (masked && !((okbits >> r) & 1u)) sq[r] = -INFINITY;
-          m = fmaxf(m, sq[r]);
-        }
+        for (int r = 0; r < 16; ++r) m = fmaxf(m, sq[r]);
         m = fmaxf(m, __shfl_xor(m, 32, 64));
         const float mm = (m == -INFINITY) ? 0.f : m;  // a query with no key keeps P = 0
         float l = 0.f;

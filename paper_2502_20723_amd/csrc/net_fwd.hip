@@ -69,8 +69,14 @@ __global__ void k_embed_table(const float* __restrict__ params, int d, int D, fl
   }
 }
 
+// Workgroup size: BF16 weights staged in LDS are shared by 8 waves (two per SIMD,
+// so that one wave's latencies overlap the other's work) when a wave's registers
+// fit in half a SIMD (one 32-row block per wave); otherwise 4 waves.
+template <class P, bool SPAN>
+constexpr int fwd_threads() { return (P::KPL == 8 && !SPAN) ? 512 : 256; }
+
 template <class P, int D, int DH, bool SPAN>
-__global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
+__global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs a) {
   constexpr int NB = D / 32;            // feature blocks
   constexpr int NBR = SPAN ? 2 : 1;     // row blocks per wave
   constexpr int HPB = 32 / DH;          // heads per 32-feature block
@@ -83,7 +89,7 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
   extern __shared__ __align__(16) char smem[];
   const int M = a.M, MB = M / 32;
   const int wtotal = 4 * D * D + 2 * D * M;
-  // LDS carve-up: [weights (BF16 only)] [b1 M] [b2 D] [table 64*D] [pool scratch 4 waves * 64 float2]
+  // LDS carve-up: [weights (BF16 only)] [b1 M] [b2 D] [table 64*D] [pool scratch: 64 float2 per wave]
   elem_t* wl = reinterpret_cast<elem_t*>(smem);
   float* b1s = reinterpret_cast<float*>(smem + (WLDS ? (size_t)wtotal * sizeof(elem_t) : 0));
   float* b2s = b1s + M;
@@ -104,7 +110,6 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
     for (int i = threadIdx.x; i < 64 * D; i += blockDim.x) tabs[i] = a.table[i];
   __syncthreads();
   const elem_t* W = WLDS ? wl : wg;
-  constexpr int FR = ST * 64 * P::KPL;  // elements per (ob, ib) fragment group
   const elem_t* Wq = W + 0 * D * D;
   const elem_t* Wk = W + 1 * D * D;
   const elem_t* Wv = W + 2 * D * D;
@@ -119,7 +124,9 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
   const int64_t ntiles = SPAN ? 2 * E : 2 * ((E + cpb - 1) / cpb);
   const float sc = a.score_scale;  // log2(e)/sqrt(dh)
 
-  // valid (query row qb*32+lr, key row kb*32+tile_idx(r, h)) pairs as bit r of okbits[qb][kb]
+  // valid (query row qb*32+lr, key row kb*32+tile_idx(r, h)) pairs as bit r of okbits[qb][kb];
+  // use_mask (uniform) is false when every pair of a tile is valid
+  const bool use_mask = SPAN ? (n < 64) : (a.masked != 0);
   uint32_t okbits[NBR][NBR];
 #pragma unroll
   for (int qb = 0; qb < NBR; ++qb)
@@ -230,11 +237,20 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
             v[rb] = P::mma(xo[rb][ib][s], ld_frag<P>(Wv, f, lane), v[rb]);  // (row x feature)
           }
       }
-      // score scale folded into q; V as operands (lane -> feature), masked to one head below
+      // score scale folded into q; per-head score operands of q and k packed once per head
+      // block; V as operands (lane -> feature), masked to one head below
+      using sop = typename P::template SOp<DH>;
+      sop qp[NBR][HPB], kp[NBR][HPB];
 #pragma unroll
-      for (int rb = 0; rb < NBR; ++rb)
+      for (int rb = 0; rb < NBR; ++rb) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) q[rb][r] *= sc;
+#pragma unroll
+        for (int j = 0; j < HPB; ++j) {
+          qp[rb][j] = P::template pack_head<DH>(q[rb], j);
+          kp[rb][j] = P::template pack_head<DH>(k[rb], j);
+        }
+      }
       op_t vop[NBR][ST];
 #pragma unroll
       for (int kb = 0; kb < NBR; ++kb)
@@ -253,12 +269,14 @@ __global__ void __launch_bounds__(256) k_fwd_layer(FwdArgs a) {
           float m = -INFINITY;
 #pragma unroll
           for (int kb = 0; kb < NBR; ++kb) {
-            st[kb] = P::template scores<DH>(k[kb], q[qb], j, f32x16{});
+            st[kb] = P::template scores_packed<DH>(kp[kb][j], qp[qb][j], f32x16{});
+            if (use_mask) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              if (!((okbits[qb][kb] >> r) & 1u)) st[kb][r] = -INFINITY;
-              m = fmaxf(m, st[kb][r]);
+              for (int r = 0; r < 16; ++r)
+                if (!((okbits[qb][kb] >> r) & 1u)) st[kb][r] = -INFINITY;
             }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) m = fmaxf(m, st[kb][r]);
           }
           m = fmaxf(m, __shfl_xor(m, 32, 64));
           const float mm = (m == -INFINITY) ? 0.f : m;  // a row with no key keeps P = 0
@@ -401,11 +419,12 @@ __global__ void k_symmetrise(const int64_t* __restrict__ E_dev, int64_t E_host, 
 template <class P, int D, int DH, bool SPAN>
 static int32_t launch_layer_t(const FwdArgs& a, int num_cus, hipStream_t st) {
   const size_t wbytes = (P::KPL == 8) ? (size_t)(4 * D * D + 2 * D * a.M) * sizeof(typename P::elem_t) : 0;
-  const size_t lds = wbytes + (size_t)(a.M + D) * 4 + (a.first ? 64 * D * 4 : 0) + 4 * 64 * sizeof(float2);
+  constexpr int threads = fwd_threads<P, SPAN>();
+  const size_t lds = wbytes + (size_t)(a.M + D) * 4 + (a.first ? 64 * D * 4 : 0) + (threads / 64) * 64 * sizeof(float2);
   auto kern = k_fwd_layer<P, D, DH, SPAN>;
   TDO_TRY(allow_full_lds((const void*)kern));
   const int blocks = num_cus * a.blocks_per_cu;
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, st, a);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
 }
