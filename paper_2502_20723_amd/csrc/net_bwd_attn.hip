@@ -146,44 +146,65 @@ __global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
 
 #pragma unroll 1
     for (int hb = 0; hb < NB; ++hb) {
-      // projections of the 32 attention features of head block hb, both orientations:
-      // *R: lane -> row, values -> features;  *F: lane -> feature, values -> rows
-      f32x16 QR = {}, KR = {}, VR = {}, OR = {}, QF = {}, KF = {}, VF = {}, OF = {};
+      // projections of the 32 attention features of head block hb, both orientations
+      // (*R: lane -> row, values -> features; *F: lane -> feature, values -> rows),
+      // formed in two groups and packed to BF16 operands right away to keep the
+      // register peak low: per-head score operands (q scaled by log2(e)/sqrt(dh)),
+      // and the feature-major tiles, masked per head below
+      bf16x8 xo[NB][ST], go[NB][ST];
 #pragma unroll
       for (int ib = 0; ib < NB; ++ib) {
         f32x16 xr, gr;
         load_xg(ib, xr, gr);
-        bf16x8 xo[ST], go[ST];
 #pragma unroll
-        for (int s = 0; s < ST; ++s) { xo[s] = op8(xr, s); go[s] = op8(gr, s); }
-#pragma unroll
-        for (int s = 0; s < ST; ++s) {
-          const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
-          const bf16x8 wq = ld8(Wq + f * 8), wk = ld8(Wk + f * 8), wv = ld8(Wv + f * 8), wo = ld8(WoT + f * 8);
-          QR = mfma16(wq, xo[s], QR);
-          QF = mfma16(xo[s], wq, QF);
-          KR = mfma16(wk, xo[s], KR);
-          KF = mfma16(xo[s], wk, KF);
-          VR = mfma16(wv, xo[s], VR);
-          VF = mfma16(xo[s], wv, VF);
-          OR = mfma16(wo, go[s], OR);  // dO, R
-          OF = mfma16(go[s], wo, OF);  // dO, F
-        }
+        for (int s = 0; s < ST; ++s) { xo[ib][s] = op8(xr, s); go[ib][s] = op8(gr, s); }
       }
-      // feature-major projections as BF16 operands (masked to one head below); score scale folded into Q
-      bf16x8 QFb[ST], KFb[ST], VFb[ST], OFb[ST];
-#pragma unroll
-      for (int s = 0; s < ST; ++s) { QFb[s] = op8(QF, s); KFb[s] = op8(KF, s); VFb[s] = op8(VF, s); OFb[s] = op8(OF, s); }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) QR[r] *= sc;
       using sop = PBF16::SOp<DH>;
-      sop QRp[HPB], KRp[HPB], VRp[HPB], ORp[HPB];  // per-head score operands, packed once
+      sop QRp[HPB], KRp[HPB], VRp[HPB], ORp[HPB];
+      bf16x8 QFb[ST], KFb[ST], VFb[ST], OFb[ST];
+      {
+        f32x16 QR = {}, KR = {}, QF = {}, KF = {};
 #pragma unroll
-      for (int j = 0; j < HPB; ++j) {
-        QRp[j] = PBF16::pack_head<DH>(QR, j);
-        KRp[j] = PBF16::pack_head<DH>(KR, j);
-        VRp[j] = PBF16::pack_head<DH>(VR, j);
-        ORp[j] = PBF16::pack_head<DH>(OR, j);
+        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+          for (int s = 0; s < ST; ++s) {
+            const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
+            const bf16x8 wq = ld8(Wq + f * 8), wk = ld8(Wk + f * 8);
+            QR = mfma16(wq, xo[ib][s], QR);
+            QF = mfma16(xo[ib][s], wq, QF);
+            KR = mfma16(wk, xo[ib][s], KR);
+            KF = mfma16(xo[ib][s], wk, KF);
+          }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) QR[r] *= sc;
+#pragma unroll
+        for (int j = 0; j < HPB; ++j) {
+          QRp[j] = PBF16::pack_head<DH>(QR, j);
+          KRp[j] = PBF16::pack_head<DH>(KR, j);
+        }
+#pragma unroll
+        for (int s = 0; s < ST; ++s) { QFb[s] = op8(QF, s); KFb[s] = op8(KF, s); }
+      }
+      {
+        f32x16 VR = {}, OR = {}, VF = {}, OF = {};  // V and dO = g W_O^T
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+          for (int s = 0; s < ST; ++s) {
+            const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
+            const bf16x8 wv = ld8(Wv + f * 8), wo = ld8(WoT + f * 8);
+            VR = mfma16(wv, xo[ib][s], VR);
+            VF = mfma16(xo[ib][s], wv, VF);
+            OR = mfma16(wo, go[ib][s], OR);
+            OF = mfma16(go[ib][s], wo, OF);
+          }
+#pragma unroll
+        for (int j = 0; j < HPB; ++j) {
+          VRp[j] = PBF16::pack_head<DH>(VR, j);
+          ORp[j] = PBF16::pack_head<DH>(OR, j);
+        }
+#pragma unroll
+        for (int s = 0; s < ST; ++s) { VFb[s] = op8(VF, s); OFb[s] = op8(OF, s); }
       }
       // key-major transposes of P and dS go through the part of this block's O and dV staging
       // that head block hb fills only after its heads are done
