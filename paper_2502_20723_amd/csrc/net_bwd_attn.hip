@@ -15,8 +15,8 @@
 // transpose of what the projections give.  The projections are therefore
 // formed in both orientations (the same weight fragments serve as A or B
 // operand), and the per-head probability and dS tiles, computed query-major,
-// are transposed to key-major through LDS as BF16 (in a part of the block's
-// staging area that is not yet in use).
+// are transposed to key-major on the matrix cores (transpose_mfma: an exact
+// product with a 0/1 permutation operand), as are the tiles staged below.
 //
 // Gradient phase (all waves).  x, g, O, dQ, dK, dV of each block are staged
 // in LDS as [feature][row] BF16 with the rows of each 16-row group in the
@@ -38,10 +38,6 @@ constexpr int FS = 40;               // row stride (bf16) of a staged [feature][
 constexpr int MAT = 64 * FS;         // one staged matrix
 enum { SX = 0, SG = 1, SQ = 2, SK = 3, SV = 4, SO = 5, NSTAGE = 6 };
 
-__device__ __forceinline__ int perm16(int row) {
-  const int q = row & 15;
-  return (row & ~15) | ((q & 4) << 1) | ((q & 8) >> 1) | (q & 3);
-}
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 __device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -52,22 +48,20 @@ __device__ __forceinline__ bf16x8 op8(const f32x16& v, int s) {
   for (int t = 0; t < 8; ++t) o[t] = (__bf16)v[8 * s + t];
   return o;
 }
-__device__ __forceinline__ bf16x8 op8m(const f32x16& v, int s, bool keep) {
-  bf16x8 o;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) o[t] = (__bf16)(keep ? v[8 * s + t] : 0.f);
-  return o;
+// Exact transpose of a 32x32 tile on the matrix cores.  With the tile as A operand
+// (lane -> m, values -> k in the result order of the k-steps) and the 0/1 matrix
+// B[k][n] = [index of k == n] (eye, built once), C = A B has lanes enumerating the
+// former value index and values the former lane index: the tile transposed,
+// returned in the MFMA result layout.  The BF16 inputs pass through unchanged.
+__device__ __forceinline__ f32x16 transpose_mfma(const bf16x8& x0, const bf16x8& x1, const bf16x8 (&eye)[2]) {
+  return mfma16(x1, eye[1], mfma16(x0, eye[0], f32x16{}));
 }
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-// R-layout tile (lane -> row, values -> features f0 + tile_idx(r, h)) into a staged [feature][row] matrix.
-__device__ __forceinline__ void stage_rows(__bf16* m, int f0, const f32x16& v, int lr, int h) {
-  const int pr = perm16(lr);
+// R-layout tile v (lane -> row, values -> features f0 + tile_idx(r, h)) into a staged
+// [feature][row position] matrix: transposed by MFMA, then two 16-byte writes per lane.
+__device__ __forceinline__ void stage_rows(__bf16* m, int f0, const f32x16& v, const bf16x8 (&eye)[2], int lr, int h) {
+  const f32x16 t = transpose_mfma(op8(v, 0), op8(v, 1), eye);  // lane -> feature f0 + lr, values -> rows
 #pragma unroll
-  for (int r = 0; r < 16; ++r) m[(f0 + tile_idx(r, h)) * FS + pr] = (__bf16)v[r];
+  for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(m + (f0 + lr) * FS + 16 * s + 8 * h) = op8(t, s);
 }
 
 }  // namespace
@@ -98,6 +92,12 @@ __global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
   const int64_t ntile = (nblk + 3) / 4;
   const float sc = a.score_scale, isd = a.inv_sqrt_dh;
   const bool masked = a.masked != 0;
+  // permutation operands of transpose_mfma: eye[s][t] = [tile_idx(8 s + t, h) == lr]
+  bf16x8 eye[2];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int t2 = 0; t2 < 8; ++t2) eye[s2][t2] = (__bf16)(tile_idx(8 * s2 + t2, h) == lr ? 1.0f : 0.0f);
   // valid (query, key) pairs of this lane's row lr against rows tile_idx(r, h): same configuration
   // slot, slot < cpb (symmetric, so the same bits serve query-major and key-major tiles)
   uint32_t okbits = 0;
@@ -140,8 +140,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
     for (int ib = 0; ib < NB; ++ib) {
       f32x16 xr, gr;
       load_xg(ib, xr, gr);
-      stage_rows(S + SX * MAT, 32 * ib, xr, lr, h);
-      stage_rows(S + SG * MAT, 32 * ib, gr, lr, h);
+      stage_rows(S + SX * MAT, 32 * ib, xr, eye, lr, h);
+      stage_rows(S + SG * MAT, 32 * ib, gr, eye, lr, h);
     }
 
 #pragma unroll 1
@@ -206,10 +206,6 @@ __global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
 #pragma unroll
         for (int s = 0; s < ST; ++s) { VFb[s] = op8(VF, s); OFb[s] = op8(OF, s); }
       }
-      // key-major transposes of P and dS go through the part of this block's O and dV staging
-      // that head block hb fills only after its heads are done
-      __bf16* TP = S + SO * MAT + 32 * hb * FS;
-      __bf16* TS = S + SV * MAT + 32 * hb * FS;
       f32x16 dQR = {}, dKR = {}, dVR = {}, AOF = {};  // dQ, dK, dV (R) and the attention output O (F)
 #pragma unroll
       for (int j = 0; j < HPB; ++j) {
@@ -247,22 +243,13 @@ __global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
         bf16x8 Pq[ST], Sq[ST];
 #pragma unroll
         for (int s = 0; s < ST; ++s) { Pq[s] = op8(sq, s); Sq[s] = op8(dpq, s); }
-        // transpose P and dS: [key][query position], read back key-major
-        wave_sync();
-        {
-          const int pq = perm16(lr);
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            TP[tile_idx(r, h) * FS + pq] = Pq[r >> 3][r & 7];
-            TS[tile_idx(r, h) * FS + pq] = Sq[r >> 3][r & 7];
-          }
-        }
-        wave_sync();
+        // key-major P and dS (lane -> key, values -> queries): exact MFMA transposes
+        const f32x16 pk = transpose_mfma(Pq[0], Pq[1], eye), sk2 = transpose_mfma(Sq[0], Sq[1], eye);
         bf16x8 Pk[ST], Sk[ST];
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
-          Pk[s] = ld8(TP + lr * FS + 16 * s + 8 * h);  // lane -> key, values -> queries
-          Sk[s] = ld8(TS + lr * FS + 16 * s + 8 * h);
+          Pk[s] = op8(pk, s);
+          Sk[s] = op8(sk2, s);
         }
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
@@ -273,11 +260,10 @@ __global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
           dVR = mfma16(mine ? OFb[s] : z, Pk[s], dVR);  // dV[k][f] = sum_q P[q][k] dO[q][f]
         }
       }
-      wave_sync();  // the transposes are consumed before the staging below reuses their space
       // stage dQ, dK, dV (R layout -> [feature][row]) and O (F layout: two 16-byte writes per lane)
-      stage_rows(S + SQ * MAT, 32 * hb, dQR, lr, h);
-      stage_rows(S + SK * MAT, 32 * hb, dKR, lr, h);
-      stage_rows(S + SV * MAT, 32 * hb, dVR, lr, h);
+      stage_rows(S + SQ * MAT, 32 * hb, dQR, eye, lr, h);
+      stage_rows(S + SK * MAT, 32 * hb, dKR, eye, lr, h);
+      stage_rows(S + SV * MAT, 32 * hb, dVR, eye, lr, h);
 #pragma unroll
       for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + (32 * hb + lr) * FS + 16 * s + 8 * h) = op8(AOF, s);
       // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T, the terms of head block hb added through the output
