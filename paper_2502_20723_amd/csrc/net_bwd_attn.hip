@@ -6,11 +6,16 @@
 //   dQ = dS K, dK = dS^T Q, dV = P^T dO;  dx = g + dQ Wq^T + dK Wk^T + dV Wv^T;
 //   dW_O += O^T g, dWq += x^T dQ, dWk += x^T dK, dWv += x^T dV.
 //
-// Work decomposition.  A workgroup of 4 waves walks tiles of 4 blocks of 32
-// rows; wave w handles block w of the tile, then owns one weight gradient
-// (w = 0..3: Wq, Wk, Wv, W_O) accumulated in registers for the whole launch.
+// Work decomposition.  A workgroup of 8 waves (two per SIMD, sharing the LDS
+// weights) walks tiles of 4 blocks of 32 rows; wave w handles head block w / 4
+// (attention features [32 (w/4), 32 (w/4) + 32)) of block w % 4 of the tile,
+// then owns rows [32 (w/4), 32 (w/4) + 32) of one weight gradient (w % 4 = 0..3:
+// Wq, Wk, Wv, W_O) accumulated in registers for the whole launch.  The two waves
+// of a block add their dx terms in turn through the output buffer: head block 0
+// writes g + its terms before the workgroup barrier, head block 1 adds its terms
+// after it, the order of a single wave walking both head blocks.
 //
-// Block phase (one wave).  Every contraction over keys or queries needs its
+// Block phase (one wave per head block).  Every contraction over keys or queries needs its
 // operands with lanes enumerating features and values enumerating rows, the
 // transpose of what the projections give.  The projections are therefore
 // formed in both orientations (the same weight fragments serve as A or B
@@ -22,7 +27,7 @@
 // in LDS as [feature][row] BF16 with the rows of each 16-row group in the
 // order of the MFMA result layout (two middle quads swapped), so that one
 // 16-byte read is a row-contraction operand.  After a workgroup barrier, wave
-// w adds the tile's 4 x 32 rows into its gradient.  Each workgroup writes its
+// w adds the tile's 4 x 32 rows into its gradient rows.  Each workgroup writes its
 // four gradients once per launch to its partial slot [4 D^2] (Wq, Wk, Wv as
 // (in, attention feature), W_O as (attention feature, out)); the slots are
 // summed in FP64 afterwards.
@@ -39,6 +44,13 @@ constexpr int MAT = 64 * FS;         // one staged matrix
 enum { SX = 0, SG = 1, SQ = 2, SK = 3, SV = 4, SO = 5, NSTAGE = 6 };
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+// 16-byte load through a buffer resource: one lane offset (VGPR) shared by all
+// fragments and a uniform offset per fragment, instead of one 64-bit address per
+// fragment kept live across the tile loop.  Reads past the resource's size return 0.
+__device__ __forceinline__ bf16x8 buf_ld8(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer access on gfx9-class devices
 __device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
@@ -56,10 +68,12 @@ __device__ __forceinline__ bf16x8 op8(const f32x16& v, int s) {
 __device__ __forceinline__ f32x16 transpose_mfma(const bf16x8& x0, const bf16x8& x1, const bf16x8 (&eye)[2]) {
   return mfma16(x1, eye[1], mfma16(x0, eye[0], f32x16{}));
 }
-// R-layout tile v (lane -> row, values -> features f0 + tile_idx(r, h)) into a staged
-// [feature][row position] matrix: transposed by MFMA, then two 16-byte writes per lane.
-__device__ __forceinline__ void stage_rows(__bf16* m, int f0, const f32x16& v, const bf16x8 (&eye)[2], int lr, int h) {
-  const f32x16 t = transpose_mfma(op8(v, 0), op8(v, 1), eye);  // lane -> feature f0 + lr, values -> rows
+// R-layout tile (lane -> row, values -> features f0 + tile_idx(r, h)), given as its two
+// BF16 operands, into a staged [feature][row position] matrix: transposed by MFMA, then
+// two 16-byte writes per lane.
+__device__ __forceinline__ void stage_ops(__bf16* m, int f0, const bf16x8& o0, const bf16x8& o1,
+                                          const bf16x8 (&eye)[2], int lr, int h) {
+  const f32x16 t = transpose_mfma(o0, o1, eye);  // lane -> feature f0 + lr, values -> rows
 #pragma unroll
   for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(m + (f0 + lr) * FS + 16 * s + 8 * h) = op8(t, s);
 }
@@ -67,23 +81,25 @@ __device__ __forceinline__ void stage_rows(__bf16* m, int f0, const f32x16& v, c
 }  // namespace
 
 template <int DH>
-__global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
+__global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
   constexpr int D = 64, NB = 2, ST = 2, HPB = 32 / DH;
   extern __shared__ __align__(16) char smem[];
   __bf16* Wl = reinterpret_cast<__bf16*>(smem);      // Wq, Wk, Wv, W_O^T fragments [4][D*D]
   __bf16* stg = Wl + 4 * D * D;                       // [4 blocks][NSTAGE][MAT]
 
   const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31, w = t >> 6;
+  const int bw = w & 3, hb = w >> 2;  // block of the tile, head block
   {
     const int4* sf = reinterpret_cast<const int4*>(a.wf);
     const int4* sb = reinterpret_cast<const int4*>(a.wb);
     int4* dl = reinterpret_cast<int4*>(Wl);
-    for (int i = t; i < 3 * D * D / 8; i += 256) dl[i] = sf[i];
-    for (int i = t; i < D * D / 8; i += 256) dl[3 * D * D / 8 + i] = sb[3 * D * D / 8 + i];
+    for (int i = t; i < 3 * D * D / 8; i += 512) dl[i] = sf[i];
+    for (int i = t; i < D * D / 8; i += 512) dl[3 * D * D / 8 + i] = sb[3 * D * D / 8 + i];
   }
   const __bf16 *Wq = Wl, *Wk = Wl + D * D, *Wv = Wl + 2 * D * D, *WoT = Wl + 3 * D * D;
-  const __bf16* Wb = reinterpret_cast<const __bf16*>(a.wb);
-  const __bf16 *WqT = Wb, *WkT = Wb + D * D, *WvT = Wb + 2 * D * D;  // global (L2)
+  // Wq^T, Wk^T, Wv^T fragments [3][D*D] BF16 in global memory (L2-resident)
+  const __amdgpu_buffer_rsrc_t WT = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.wb), (short)0,
+                                                                      3 * D * D * 2, RSRC_WORD3);
   __syncthreads();
 
   const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
@@ -107,225 +123,216 @@ __global__ void __launch_bounds__(256) k_bwd_attn_bf16(BwdArgs a) {
     okbits |= (other == lr / n && other < cpb) ? (1u << r) : 0u;
   }
 
-  f32x16 dW[NB][NB];
+  f32x16 dW[NB];  // rows [32 hb, 32 hb + 32) of weight gradient bw
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) dW[i][j] = f32x16{};
+  for (int j = 0; j < NB; ++j) dW[j] = f32x16{};
 
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    // ================= block phase: block gb of wave w
-    const int64_t gb = 4 * tile + w;
+    // ================= block phase: head block hb of block gb
+    const int64_t gb = 4 * tile + bw;
     const bool valid = gb < nblk;
-    __bf16* S = stg + w * NSTAGE * MAT;
-    // x (layer input) and g (gradient of the sub-layer output) of the block, lane -> row
-    auto load_xg = [&](int ib, f32x16& xr, f32x16& gr) {
+    __bf16* S = stg + bw * NSTAGE * MAT;
+    // x (layer input, saved in BF16) and g (gradient of the sub-layer output) of the block as
+    // BF16 operands, lane -> row, values -> features 32 ib + tile_idx(8 s + t, h)
+    bf16x8 xo[NB][ST], go[NB][ST];
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
       if (valid) {
         const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_x) + ((gb * NB + ib) * 64 + lane) * 16;
-        const bf16x8 x0 = ld8(xs), x1 = ld8(xs + 8);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) { xr[k] = (float)x0[k]; xr[8 + k] = (float)x1[k]; }
+        xo[ib][0] = ld8(xs);
+        xo[ib][1] = ld8(xs + 8);
         const float4* gs = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + ib) * 64 + lane) * 16);
+        f32x16 gr;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const float4 v = gs[q];
           gr[4 * q] = v.x; gr[4 * q + 1] = v.y; gr[4 * q + 2] = v.z; gr[4 * q + 3] = v.w;
         }
+        go[ib][0] = op8(gr, 0);
+        go[ib][1] = op8(gr, 1);
       } else {
-        xr = f32x16{};
-        gr = f32x16{};
+        xo[ib][0] = xo[ib][1] = go[ib][0] = go[ib][1] = bf16x8{};
       }
-    };
+    }
+    // the wave of head block 0 stages x, the other g
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) {
-      f32x16 xr, gr;
-      load_xg(ib, xr, gr);
-      stage_rows(S + SX * MAT, 32 * ib, xr, eye, lr, h);
-      stage_rows(S + SG * MAT, 32 * ib, gr, eye, lr, h);
+      if (hb == 0) stage_ops(S + SX * MAT, 32 * ib, xo[ib][0], xo[ib][1], eye, lr, h);
+      else stage_ops(S + SG * MAT, 32 * ib, go[ib][0], go[ib][1], eye, lr, h);
     }
 
-#pragma unroll 1
-    for (int hb = 0; hb < NB; ++hb) {
-      // projections of the 32 attention features of head block hb, both orientations
-      // (*R: lane -> row, values -> features; *F: lane -> feature, values -> rows),
-      // formed in two groups and packed to BF16 operands right away to keep the
-      // register peak low: per-head score operands (q scaled by log2(e)/sqrt(dh)),
-      // and the feature-major tiles, masked per head below
-      bf16x8 xo[NB][ST], go[NB][ST];
+    // projections of the 32 attention features of head block hb, both orientations
+    // (*R: lane -> row, values -> features; *F: lane -> feature, values -> rows),
+    // formed in two groups and packed to BF16 operands right away to keep the
+    // register peak low: per-head score operands (q scaled by log2(e)/sqrt(dh)),
+    // and the feature-major tiles, masked per head below
+    using sop = PBF16::SOp<DH>;
+    sop QRp[HPB], KRp[HPB], VRp[HPB], ORp[HPB];
+    bf16x8 QFb[ST], KFb[ST], VFb[ST], OFb[ST];
+    {
+      f32x16 QR = {}, KR = {}, QF = {}, KF = {};
 #pragma unroll
-      for (int ib = 0; ib < NB; ++ib) {
-        f32x16 xr, gr;
-        load_xg(ib, xr, gr);
+      for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
-        for (int s = 0; s < ST; ++s) { xo[ib][s] = op8(xr, s); go[ib][s] = op8(gr, s); }
-      }
-      using sop = PBF16::SOp<DH>;
-      sop QRp[HPB], KRp[HPB], VRp[HPB], ORp[HPB];
-      bf16x8 QFb[ST], KFb[ST], VFb[ST], OFb[ST];
-      {
-        f32x16 QR = {}, KR = {}, QF = {}, KF = {};
-#pragma unroll
-        for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-          for (int s = 0; s < ST; ++s) {
-            const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
-            const bf16x8 wq = ld8(Wq + f * 8), wk = ld8(Wk + f * 8);
-            QR = mfma16(wq, xo[ib][s], QR);
-            QF = mfma16(xo[ib][s], wq, QF);
-            KR = mfma16(wk, xo[ib][s], KR);
-            KF = mfma16(xo[ib][s], wk, KF);
-          }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) QR[r] *= sc;
-#pragma unroll
-        for (int j = 0; j < HPB; ++j) {
-          QRp[j] = PBF16::pack_head<DH>(QR, j);
-          KRp[j] = PBF16::pack_head<DH>(KR, j);
+        for (int s = 0; s < ST; ++s) {
+          const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
+          const bf16x8 wq = ld8(Wq + f * 8), wk = ld8(Wk + f * 8);
+          QR = mfma16(wq, xo[ib][s], QR);
+          QF = mfma16(xo[ib][s], wq, QF);
+          KR = mfma16(wk, xo[ib][s], KR);
+          KF = mfma16(xo[ib][s], wk, KF);
         }
 #pragma unroll
-        for (int s = 0; s < ST; ++s) { QFb[s] = op8(QF, s); KFb[s] = op8(KF, s); }
-      }
-      {
-        f32x16 VR = {}, OR = {}, VF = {}, OF = {};  // V and dO = g W_O^T
-#pragma unroll
-        for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-          for (int s = 0; s < ST; ++s) {
-            const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
-            const bf16x8 wv = ld8(Wv + f * 8), wo = ld8(WoT + f * 8);
-            VR = mfma16(wv, xo[ib][s], VR);
-            VF = mfma16(xo[ib][s], wv, VF);
-            OR = mfma16(wo, go[ib][s], OR);
-            OF = mfma16(go[ib][s], wo, OF);
-          }
-#pragma unroll
-        for (int j = 0; j < HPB; ++j) {
-          VRp[j] = PBF16::pack_head<DH>(VR, j);
-          ORp[j] = PBF16::pack_head<DH>(OR, j);
-        }
-#pragma unroll
-        for (int s = 0; s < ST; ++s) { VFb[s] = op8(VF, s); OFb[s] = op8(OF, s); }
-      }
-      f32x16 dQR = {}, dKR = {}, dVR = {}, AOF = {};  // dQ, dK, dV (R) and the attention output O (F)
+      for (int r = 0; r < 16; ++r) QR[r] *= sc;
 #pragma unroll
       for (int j = 0; j < HPB; ++j) {
-        const bool mine = (lr / DH) == j;
-        // query-major tiles: lane -> query lr, values -> keys tile_idx(r, h)
-        f32x16 sq = PBF16::scores_packed<DH>(KRp[j], QRp[j], f32x16{});
-        f32x16 dpq = PBF16::scores_packed<DH>(VRp[j], ORp[j], f32x16{});
-        if (masked) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r)
-            if (!((okbits >> r) & 1u)) sq[r] = -INFINITY;
-        }
-        float m = -INFINITY;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) m = fmaxf(m, sq[r]);
-        m = fmaxf(m, __shfl_xor(m, 32, 64));
-        const float mm = (m == -INFINITY) ? 0.f : m;  // a query with no key keeps P = 0
-        float l = 0.f;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          sq[r] = __builtin_amdgcn_exp2f(sq[r] - mm);
-          l += sq[r];
-        }
-        l += __shfl_xor(l, 32, 64);
-        const float il = l > 0.f ? 1.0f / l : 0.f;
-        float dl = 0.f;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          sq[r] *= il;  // P
-          dl += sq[r] * dpq[r];
-        }
-        dl += __shfl_xor(dl, 32, 64);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) dpq[r] = sq[r] * (dpq[r] - dl) * isd;  // dS
-        bf16x8 Pq[ST], Sq[ST];
-#pragma unroll
-        for (int s = 0; s < ST; ++s) { Pq[s] = op8(sq, s); Sq[s] = op8(dpq, s); }
-        // key-major P and dS (lane -> key, values -> queries): exact MFMA transposes
-        const f32x16 pk = transpose_mfma(Pq[0], Pq[1], eye), sk2 = transpose_mfma(Sq[0], Sq[1], eye);
-        bf16x8 Pk[ST], Sk[ST];
-#pragma unroll
-        for (int s = 0; s < ST; ++s) {
-          Pk[s] = op8(pk, s);
-          Sk[s] = op8(sk2, s);
-        }
-#pragma unroll
-        for (int s = 0; s < ST; ++s) {
-          const bf16x8 z = {};
-          AOF = mfma16(Pq[s], mine ? VFb[s] : z, AOF);  // O[q][f]  = sum_k P[q][k] V[k][f]
-          dQR = mfma16(mine ? KFb[s] : z, Sq[s], dQR);  // dQ[q][f] = sum_k dS[q][k] K[k][f]
-          dKR = mfma16(mine ? QFb[s] : z, Sk[s], dKR);  // dK[k][f] = sum_q dS[q][k] Q[q][f]
-          dVR = mfma16(mine ? OFb[s] : z, Pk[s], dVR);  // dV[k][f] = sum_q P[q][k] dO[q][f]
-        }
+        QRp[j] = PBF16::pack_head<DH>(QR, j);
+        KRp[j] = PBF16::pack_head<DH>(KR, j);
       }
-      // stage dQ, dK, dV (R layout -> [feature][row]) and O (F layout: two 16-byte writes per lane)
-      stage_rows(S + SQ * MAT, 32 * hb, dQR, eye, lr, h);
-      stage_rows(S + SK * MAT, 32 * hb, dKR, eye, lr, h);
-      stage_rows(S + SV * MAT, 32 * hb, dVR, eye, lr, h);
 #pragma unroll
-      for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + (32 * hb + lr) * FS + 16 * s + 8 * h) = op8(AOF, s);
-      // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T, the terms of head block hb added through the output
-      // buffer (each lane rereads only what it wrote)
-      if (valid) {
+      for (int s = 0; s < ST; ++s) { QFb[s] = op8(QF, s); KFb[s] = op8(KF, s); }
+    }
+    {
+      f32x16 VR = {}, OR = {}, VF = {}, OF = {};  // V and dO = g W_O^T
 #pragma unroll
-        for (int ob = 0; ob < NB; ++ob) {
-          f32x16 acc;
-          const float4* src = reinterpret_cast<const float4*>((hb == 0 ? a.g_in : a.g_out) + ((gb * NB + ob) * 64 + lane) * 16);
+      for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float4 v = src[q];
-            acc[4 * q] = v.x; acc[4 * q + 1] = v.y; acc[4 * q + 2] = v.z; acc[4 * q + 3] = v.w;
-          }
-#pragma unroll
-          for (int s = 0; s < ST; ++s) {
-            const int f = ((ob * NB + hb) * ST + s) * 64 + lane;
-            acc = mfma16(ld8(WqT + f * 8), op8(dQR, s), acc);
-            acc = mfma16(ld8(WkT + f * 8), op8(dKR, s), acc);
-            acc = mfma16(ld8(WvT + f * 8), op8(dVR, s), acc);
-          }
-          float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + ob) * 64 + lane) * 16);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) dst[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+        for (int s = 0; s < ST; ++s) {
+          const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
+          const bf16x8 wv = ld8(Wv + f * 8), wo = ld8(WoT + f * 8);
+          VR = mfma16(wv, xo[ib][s], VR);
+          VF = mfma16(xo[ib][s], wv, VF);
+          OR = mfma16(wo, go[ib][s], OR);
+          OF = mfma16(go[ib][s], wo, OF);
         }
+#pragma unroll
+      for (int j = 0; j < HPB; ++j) {
+        VRp[j] = PBF16::pack_head<DH>(VR, j);
+        ORp[j] = PBF16::pack_head<DH>(OR, j);
+      }
+#pragma unroll
+      for (int s = 0; s < ST; ++s) { VFb[s] = op8(VF, s); OFb[s] = op8(OF, s); }
+    }
+    f32x16 dQR = {}, dKR = {}, dVR = {}, AOF = {};  // dQ, dK, dV (R) and the attention output O (F)
+#pragma unroll
+    for (int j = 0; j < HPB; ++j) {
+      const bool mine = (lr / DH) == j;
+      // query-major tiles: lane -> query lr, values -> keys tile_idx(r, h)
+      f32x16 sq = PBF16::scores_packed<DH>(KRp[j], QRp[j], f32x16{});
+      f32x16 dpq = PBF16::scores_packed<DH>(VRp[j], ORp[j], f32x16{});
+      if (masked) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (!((okbits >> r) & 1u)) sq[r] = -INFINITY;
+      }
+      float m = -INFINITY;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) m = fmaxf(m, sq[r]);
+      m = fmaxf(m, __shfl_xor(m, 32, 64));
+      const float mm = (m == -INFINITY) ? 0.f : m;  // a query with no key keeps P = 0
+      float l = 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        sq[r] = __builtin_amdgcn_exp2f(sq[r] - mm);
+        l += sq[r];
+      }
+      l += __shfl_xor(l, 32, 64);
+      const float il = l > 0.f ? 1.0f / l : 0.f;
+      float dl = 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        sq[r] *= il;  // P
+        dl += sq[r] * dpq[r];
+      }
+      dl += __shfl_xor(dl, 32, 64);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) dpq[r] = sq[r] * (dpq[r] - dl) * isd;  // dS
+      bf16x8 Pq[ST], Sq[ST];
+#pragma unroll
+      for (int s = 0; s < ST; ++s) { Pq[s] = op8(sq, s); Sq[s] = op8(dpq, s); }
+      // key-major P and dS (lane -> key, values -> queries): exact MFMA transposes
+      const f32x16 pk = transpose_mfma(Pq[0], Pq[1], eye), sk2 = transpose_mfma(Sq[0], Sq[1], eye);
+      bf16x8 Pk[ST], Sk[ST];
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+        Pk[s] = op8(pk, s);
+        Sk[s] = op8(sk2, s);
+      }
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+        const bf16x8 z = {};
+        AOF = mfma16(Pq[s], mine ? VFb[s] : z, AOF);  // O[q][f]  = sum_k P[q][k] V[k][f]
+        dQR = mfma16(mine ? KFb[s] : z, Sq[s], dQR);  // dQ[q][f] = sum_k dS[q][k] K[k][f]
+        dKR = mfma16(mine ? QFb[s] : z, Sk[s], dKR);  // dK[k][f] = sum_q dS[q][k] Q[q][f]
+        dVR = mfma16(mine ? OFb[s] : z, Pk[s], dVR);  // dV[k][f] = sum_q P[q][k] dO[q][f]
       }
     }
-    __syncthreads();
+    // stage dQ, dK, dV (R layout -> [feature][row]) and O (F layout: two 16-byte writes per lane)
+    bf16x8 dq[ST], dk[ST], dv[ST];
+#pragma unroll
+    for (int s = 0; s < ST; ++s) { dq[s] = op8(dQR, s); dk[s] = op8(dKR, s); dv[s] = op8(dVR, s); }
+    stage_ops(S + SQ * MAT, 32 * hb, dq[0], dq[1], eye, lr, h);
+    stage_ops(S + SK * MAT, 32 * hb, dk[0], dk[1], eye, lr, h);
+    stage_ops(S + SV * MAT, 32 * hb, dv[0], dv[1], eye, lr, h);
+#pragma unroll
+    for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + (32 * hb + lr) * FS + 16 * s + 8 * h) = op8(AOF, s);
+    // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T: the terms of head block hb added to src (g for
+    // head block 0; for head block 1 what head block 0 wrote, each lane rereading only
+    // what the other wave's same lane wrote)
+    auto add_dx = [&](const float* src) {
+#pragma unroll
+      for (int ob = 0; ob < NB; ++ob) {
+        f32x16 acc;
+        const float4* sp = reinterpret_cast<const float4*>(src + ((gb * NB + ob) * 64 + lane) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 v = sp[q];
+          acc[4 * q] = v.x; acc[4 * q + 1] = v.y; acc[4 * q + 2] = v.z; acc[4 * q + 3] = v.w;
+        }
+        const int voff = (hb * ST * 64 + lane) * 16;  // fragment ((ob NB + hb) ST + s) of each matrix
+#pragma unroll
+        for (int s = 0; s < ST; ++s) {
+          const int so = (ob * NB * ST + s) * 64 * 16;
+          acc = mfma16(buf_ld8(WT, voff, so), dq[s], acc);
+          acc = mfma16(buf_ld8(WT, voff, so + D * D * 2), dk[s], acc);
+          acc = mfma16(buf_ld8(WT, voff, so + 2 * D * D * 2), dv[s], acc);
+        }
+        float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + ob) * 64 + lane) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+      }
+    };
+    if (hb == 0 && valid) add_dx(a.g_in);
+    __syncthreads();  // staging complete; head block 0's dx terms written
+    if (hb == 1 && valid) add_dx(a.g_out);
 
-    // ================= gradient phase: wave w adds the tile's rows into its weight gradient
+    // ================= gradient phase: wave w adds the tile's rows into its weight gradient rows
     {
-      const int am = (w < 3) ? SX : SO;       // A operand: x (for Wq, Wk, Wv) or O (for W_O)
-      const int bm = (w < 3) ? SQ + w : SG;   // B operand: dQ, dK, dV or g
+      const int am = (bw < 3) ? SX : SO;       // A operand: x (for Wq, Wk, Wv) or O (for W_O)
+      const int bm = (bw < 3) ? SQ + bw : SG;  // B operand: dQ, dK, dV or g
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const __bf16* A = stg + (b * NSTAGE + am) * MAT;
         const __bf16* B = stg + (b * NSTAGE + bm) * MAT;
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
-          bf16x8 av[NB], bv[NB];
+          const bf16x8 av = ld8(A + (32 * hb + lr) * FS + 16 * s + 8 * h);
+          bf16x8 bv[NB];
 #pragma unroll
-          for (int i = 0; i < NB; ++i) {
-            av[i] = ld8(A + (32 * i + lr) * FS + 16 * s + 8 * h);
-            bv[i] = ld8(B + (32 * i + lr) * FS + 16 * s + 8 * h);
-          }
+          for (int j = 0; j < NB; ++j) bv[j] = ld8(B + (32 * j + lr) * FS + 16 * s + 8 * h);
 #pragma unroll
-          for (int i = 0; i < NB; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) dW[i][j] = mfma16(av[i], bv[j], dW[i][j]);
+          for (int j = 0; j < NB; ++j) dW[j] = mfma16(av, bv[j], dW[j]);
         }
       }
     }
     __syncthreads();
   }
 
-  float* part = a.partial + (int64_t)blockIdx.x * 4 * D * D + (int64_t)w * D * D;
+  float* part = a.partial + (int64_t)blockIdx.x * 4 * D * D + (int64_t)bw * D * D;
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
+  for (int j = 0; j < NB; ++j)
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) part[(32 * i + tile_idx(r, h)) * D + 32 * j + lr] = dW[i][j][r];
+    for (int r = 0; r < 16; ++r) part[(32 * hb + tile_idx(r, h)) * D + 32 * j + lr] = dW[j][r];
 }
 
 size_t bwd_attn_bf16_lds() {
@@ -336,9 +343,11 @@ bool bwd_attn_bf16_supported(int d, int D, int DH, bool span) { return d == 64 &
 
 int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t st) {
   const size_t lds = bwd_attn_bf16_lds();
+  // the second head block's wave rereads the output written by the first
+  TDO_CHECK(a.g_in != a.g_out, TDO_EINVAL, "BF16 attention backward cannot run in place");
   auto go = [&](auto kern) -> int32_t {
     TDO_TRY(allow_full_lds((const void*)kern));
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(512), lds, st, a);
     TDO_HIP(hipGetLastError());
     return TDO_OK;
   };

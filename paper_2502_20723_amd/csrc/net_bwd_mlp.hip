@@ -98,14 +98,13 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   __bf16* GT = GA + RT * XS;                      // [D][XS]    g^T, permuted rows
   __bf16* DU = GT + D * XS;                       // [RT][DUS]  du, row-major
   __bf16* W1s = DU + RT * DUS;                    // [D][DUS]   W1 (operand of dx = du W1^T)
-  float* db2s = reinterpret_cast<float*>(W1s + D * DUS);  // [D]
+  float* db2s = reinterpret_cast<float*>(W1s + D * DUS);  // [2 blocks of the tile][D]
 
   const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31, w = t >> 6;
   const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
   const RowMap rm{a.n, a.cpb, a.span != 0};
   const int64_t nblk = a.span ? 4 * E : 2 * ((E + a.cpb - 1) / a.cpb);
   const int64_t ntile = (nblk + 1) / 2;
-  if (t < D) db2s[t] = 0.f;
 
   // ---- weights of this wave, as BF16 MFMA operands (read once per launch)
   const int hid0 = HW * w;  // first hidden unit owned by this wave
@@ -122,7 +121,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
       }
   const int rb3 = w >> 1, it3 = w & 1;  // tile of dx formed by this wave
   for (int i = t; i < D * M; i += 256) W1s[(i / M) * DUS + i % M] = (__bf16)a.w1[i];
-  __syncthreads();  // W1s and db2s initialised before any use
+  __syncthreads();  // W1s initialised before any use
   float bias[HT];
 #pragma unroll
   for (int nt = 0; nt < HT; ++nt) bias[nt] = a.b1[hid0 + 32 * nt + lr];
@@ -265,14 +264,21 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
     const float v = db1[nt] + __shfl_xor(db1[nt], 32, 64);
     if (h == 0) part[2 * D * M + hid0 + 32 * nt + lr] = v;
   }
+  // db2: the 32 rows of each lane half summed by a fixed butterfly, then the two
+  // blocks of the tile in a fixed order (deterministic, unlike atomics)
 #pragma unroll
-  for (int r = 0; r < 16; ++r) atomicAdd(db2s + 32 * sob + tile_idx(r, sh), db2[r]);
+  for (int r = 0; r < 16; ++r) {
+    float v = db2[r];
+#pragma unroll
+    for (int m = 1; m < 32; m <<= 1) v += __shfl_xor(v, m, 64);
+    if ((sl & 31) == 0) db2s[sb * D + 32 * sob + tile_idx(r, sh)] = v;
+  }
   __syncthreads();
-  if (t < D) part[2 * D * M + M + t] = db2s[t];
+  if (t < D) part[2 * D * M + M + t] = db2s[t] + db2s[D + t];
 }
 
 size_t bwd_mlp_bf16_lds(int M) {
-  return (size_t)(2 * RT * XS + 2 * 64 * XS + (RT + 64) * (M + 8)) * sizeof(__bf16) + 64 * sizeof(float);
+  return (size_t)(2 * RT * XS + 2 * 64 * XS + (RT + 64) * (M + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float);
 }
 
 bool bwd_mlp_bf16_supported(int d, int D, int M) { return d == 64 && D == 64 && (M == 128 || M == 256); }

@@ -160,3 +160,24 @@ def test_gradient_matches_finite_differences(gpu):
     err = rel_l2(grad[idx], fd)
     print(f"FD check on 64 parameters: rel L2 {err:.3e} (|g| {np.linalg.norm(fd):.3e})")
     assert err < 1e-3
+
+
+@pytest.mark.parametrize("name,n,B", [("ising_n32", 32, 2048), ("xyz_n16", 16, 1024), ("ising_n32", 27, 300)])
+def test_bf16_gradient_reproducible(gpu, name, n, B):
+    """BF16, width 64, n <= 32 (the register-gradient backward kernels): repeated
+    calls give the same loss and gradient.  Every weight
+    gradient is formed by fixed owners in a fixed order; only the output head's FP64
+    sums use atomics (order-dependent in the last bits)."""
+    arch = ARCH[name]
+    model = model_of(name, n)
+    params = cuda(synth.params(arch, 41, "mid"))
+    cfg = cuda(synth.configs(n, B, 42))
+    ctx = gpu.Ctx(0)
+    runs = [ctx.loss_grad(arch, params, model, cfg, None, "bf16", "B") for _ in range(3)]
+    torch.cuda.synchronize()
+    l0, g0 = float(runs[0][0][0]), runs[0][1]
+    nh = 2 * arch["d"] + 2  # head_w, head_b (the last parameters)
+    for l, g, _ in runs[1:]:
+        assert float(l[0]) == l0
+        assert torch.equal(g[:-nh], g0[:-nh])
+        assert rel_l2(g[-nh:].cpu().numpy(), g0[-nh:].cpu().numpy()) < 1e-13
