@@ -173,6 +173,21 @@ struct RowMap {
   }
 };
 
+// Sum and maximum of a value over the two halves of the wave (lanes l and l ^ 32) on
+// the vector ALU (v_permlane32_swap: after swapping the upper half of one copy
+// with the lower half of another, the two registers hold the lower and upper
+// halves' values in every lane), instead of a round trip through the LDS
+// crossbar.  Both operations are commutative, so every lane gets the same bits as
+// x + shfl_xor(x, 32).  All 64 lanes must be active.
+__device__ __forceinline__ float xor32_sum(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xor32_max(float x) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+
 // Exact ReLU of the feed-forward sub-layer.
 __device__ __forceinline__ float relu(float x) { return x > 0.f ? x : 0.f; }
 

@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       float m = -INFINITY;
 #pragma unroll
       for (int r = 0; r < 16; ++r) m = fmaxf(m, sq[r]);
-      m = fmaxf(m, __shfl_xor(m, 32, 64));
+      m = xor32_max(m);
       const float mm = (m == -INFINITY) ? 0.f : m;  // a query with no key keeps P = 0
       float l = 0.f;
 #pragma unroll
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         sq[r] = __builtin_amdgcn_exp2f(sq[r] - mm);
         l += sq[r];
       }
-      l += __shfl_xor(l, 32, 64);
+      l = xor32_sum(l);
       const float il = l > 0.f ? 1.0f / l : 0.f;
       float dl = 0.f;
 #pragma unroll
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         sq[r] *= il;  // P
         dl += sq[r] * dpq[r];
       }
-      dl += __shfl_xor(dl, 32, 64);
+      dl = xor32_sum(dl);
 #pragma unroll
       for (int r = 0; r < 16; ++r) dpq[r] = sq[r] * (dpq[r] - dl) * isd;  // dS
       bf16x8 Pq[ST], Sq[ST];

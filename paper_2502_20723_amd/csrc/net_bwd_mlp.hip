@@ -9,13 +9,16 @@
 // [w M/4, (w+1) M/4), i.e. its columns of dW1 and rows of dW2, so no
 // gradient is ever added through memory until the launch ends.  Per tile:
 //   1. the tile's x and g are staged in LDS twice: row-major (operands of
-//      the contractions over features) and transposed with the rows of each
-//      16-row group reordered so that one 16-byte read returns exactly the
-//      rows an MFMA result tile holds in its values (operands of the
-//      contractions over rows);
+//      the contractions over features) and transposed (operands of the
+//      contractions over rows), the transpose formed exactly on the matrix
+//      cores.  Inside every 16-element group the index order is that of the
+//      MFMA result layout (the two middle quads swapped, perm16), so that every
+//      tile is written and read with 16-byte accesses; the weight operands
+//      and W1's LDS copy take the same order along the contracted index;
 //   2. each wave recomputes u and dh for its hidden units in the
 //      (row x hidden) orientation, whose registers are directly the row-
-//      contraction operands of dW1 and dW2, and writes du to LDS;
+//      contraction operands of dW1 and dW2, and writes du (transposed on the
+//      matrix cores) to LDS;
 //   3. each wave forms one 32x32 tile of dx = g + du W1^T from the du of all
 //      hidden units.
 // The workgroup's gradients are written once per launch to its slot of the
@@ -51,6 +54,14 @@ __device__ __forceinline__ bf16x8 op8(const f32x16& v, int s) {
 #pragma unroll
   for (int t = 0; t < 8; ++t) o[t] = (__bf16)v[8 * s + t];
   return o;
+}
+
+// Exact transpose of a 32x32 tile on the matrix cores, given as the two BF16
+// operands of its R layout (lane -> m, values -> tile_idx(8 s + t, h)): the
+// product with the 0/1 matrix eye[k][n] = [tile_idx(k) == n] returns lane ->
+// former value index, values -> former lane index (result layout).
+__device__ __forceinline__ f32x16 transpose_mfma(const bf16x8& x0, const bf16x8& x1, const bf16x8 (&eye)[2]) {
+  return mfma16(x1, eye[1], mfma16(x0, eye[0], f32x16{}));
 }
 
 }  // namespace
@@ -96,8 +107,8 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   __bf16* XT = XA + RT * XS;                      // [D][XS]    x^T, permuted rows
   __bf16* GA = XT + D * XS;                       // [RT][XS]   g, row-major
   __bf16* GT = GA + RT * XS;                      // [D][XS]    g^T, permuted rows
-  __bf16* DU = GT + D * XS;                       // [RT][DUS]  du, row-major
-  __bf16* W1s = DU + RT * DUS;                    // [D][DUS]   W1 (operand of dx = du W1^T)
+  __bf16* DU = GT + D * XS;                       // [RT][DUS]  du, row-major, hidden units in perm16 order
+  __bf16* W1s = DU + RT * DUS;                    // [D][DUS]   W1 (operand of dx = du W1^T), same order
   float* db2s = reinterpret_cast<float*>(W1s + D * DUS);  // [2 blocks of the tile][D]
 
   const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31, w = t >> 6;
@@ -115,12 +126,18 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const int hid = hid0 + 32 * nt + lr, f = 16 * s + 8 * h + k;
+        const int hid = hid0 + 32 * nt + lr, f = perm16(16 * s + 8 * h + k);  // order of XA, GA
         w1b[nt][s][k] = (__bf16)a.w1[f * M + hid];  // B[k = in][n = hidden] = W1[in][hidden]
         w2b[nt][s][k] = (__bf16)a.w2[hid * D + f];  // B[k = out][n = hidden] = W2[hidden][out]
       }
   const int rb3 = w >> 1, it3 = w & 1;  // tile of dx formed by this wave
-  for (int i = t; i < D * M; i += 256) W1s[(i / M) * DUS + i % M] = (__bf16)a.w1[i];
+  for (int i = t; i < D * M; i += 256) W1s[(i / M) * DUS + perm16(i % M)] = (__bf16)a.w1[i];
+  // permutation operands of transpose_mfma: eye[s][t] = [tile_idx(8 s + t, h) == lr]
+  bf16x8 eye[2];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int t2 = 0; t2 < 8; ++t2) eye[s2][t2] = (__bf16)(tile_idx(8 * s2 + t2, h) == lr ? 1.0f : 0.0f);
   __syncthreads();  // W1s initialised before any use
   float bias[HT];
 #pragma unroll
@@ -141,37 +158,37 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   const int sb = t >> 7, sob = (t >> 6) & 1, sl = lane, srow = 32 * sb + (sl & 31), sh = sl >> 5;
 
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    // ---- 1. stage x and g of the tile
+    // ---- 1. stage x and g of the tile (wave = role (block sb, feature block sob))
     {
       const int64_t gb = 2 * tile + sb;
-      float x[16], g[16];
+      bf16x8 xo[2], go[2];
       if (gb < nblk) {
         const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_mid) + ((gb * NB + sob) * 64 + sl) * 16;
-        const bf16x8 x0 = ld8(xs), x1 = ld8(xs + 8);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) { x[k] = (float)x0[k]; x[8 + k] = (float)x1[k]; }
+        xo[0] = ld8(xs);
+        xo[1] = ld8(xs + 8);
+        float g[16];
         grad_tile<NB>(a, rm, E, gb, sob, sl, g);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) db2[r] += g[r];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int k = 0; k < 8; ++k) go[s][k] = (__bf16)g[8 * s + k];
       } else {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) x[r] = g[r] = 0.f;
+        xo[0] = xo[1] = go[0] = go[1] = bf16x8{};
       }
+      // row-major: value t of operand s is feature 32 sob + tile_idx(8 s + t, sh), position 32 sob + 16 s + 8 sh + t
 #pragma unroll
-      for (int r = 0; r < 16; ++r) db2[r] += g[r];
-      const int pr = perm16(srow);
+      for (int s = 0; s < 2; ++s) {
+        *reinterpret_cast<bf16x8*>(XA + srow * XS + 32 * sob + 16 * s + 8 * sh) = xo[s];
+        *reinterpret_cast<bf16x8*>(GA + srow * XS + 32 * sob + 16 * s + 8 * sh) = go[s];
+      }
+      // transposed: lane -> feature 32 sob + lr, values -> rows of block sb in perm16 order
+      const f32x16 xt = transpose_mfma(xo[0], xo[1], eye), gt = transpose_mfma(go[0], go[1], eye);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int f0 = 32 * sob + 8 * j + 4 * sh;
-        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-        bf16x4 xv, gv;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          xv[c] = (__bf16)x[4 * j + c];
-          gv[c] = (__bf16)g[4 * j + c];
-          XT[(f0 + c) * XS + pr] = xv[c];
-          GT[(f0 + c) * XS + pr] = gv[c];
-        }
-        *reinterpret_cast<bf16x4*>(XA + srow * XS + f0) = xv;
-        *reinterpret_cast<bf16x4*>(GA + srow * XS + f0) = gv;
+      for (int s = 0; s < 2; ++s) {
+        *reinterpret_cast<bf16x8*>(XT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = op8(xt, s);
+        *reinterpret_cast<bf16x8*>(GT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = op8(gt, s);
       }
     }
     __syncthreads();
@@ -202,6 +219,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
           dh[nt][r] = d;                   // du
           db1[nt] += d;
         }
+      bf16x8 duo[HT][2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int pos = 32 * rb + 16 * s + 8 * h;
@@ -213,18 +231,23 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
         }
 #pragma unroll
         for (int nt = 0; nt < HT; ++nt) {
-          const bf16x8 duo = op8(dh[nt], s), ho = op8(u[nt], s);
+          duo[nt][s] = op8(dh[nt], s);
+          const bf16x8 ho = op8(u[nt], s);
 #pragma unroll
           for (int i = 0; i < NB; ++i) {
-            dW1[i][nt] = mfma16(xt[i], duo, dW1[i][nt]);  // (in x hidden)
-            dW2[nt][i] = mfma16(ho, gt[i], dW2[nt][i]);   // (hidden x out)
+            dW1[i][nt] = mfma16(xt[i], duo[nt][s], dW1[i][nt]);  // (in x hidden)
+            dW2[nt][i] = mfma16(ho, gt[i], dW2[nt][i]);          // (hidden x out)
           }
         }
       }
+      // du transposed (lane -> row, values -> hidden units in perm16 order), 16-byte writes
 #pragma unroll
-      for (int nt = 0; nt < HT; ++nt)
+      for (int nt = 0; nt < HT; ++nt) {
+        const f32x16 dut = transpose_mfma(duo[nt][0], duo[nt][1], eye);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) DU[(32 * rb + tile_idx(r, h)) * DUS + hid0 + 32 * nt + lr] = (__bf16)dh[nt][r];
+        for (int s = 0; s < 2; ++s)
+          *reinterpret_cast<bf16x8*>(DU + (32 * rb + lr) * DUS + hid0 + 32 * nt + 16 * s + 8 * h) = op8(dut, s);
+      }
     }
     __syncthreads();
 

@@ -278,7 +278,7 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
 #pragma unroll
             for (int r = 0; r < 16; ++r) m = fmaxf(m, st[kb][r]);
           }
-          m = fmaxf(m, __shfl_xor(m, 32, 64));
+          m = xor32_max(m);
           const float mm = (m == -INFINITY) ? 0.f : m;  // a row with no key keeps P = 0
           float l = 0.f;
 #pragma unroll
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
               st[kb][r] = p;
               l += p;
             }
-          l += __shfl_xor(l, 32, 64);
+          l = xor32_sum(l);
           invl[qb][j] = l > 0.f ? 1.0f / l : 0.f;
 #pragma unroll
           for (int kb = 0; kb < NBR; ++kb)
@@ -374,8 +374,8 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
             f1 += x[rb][ob][r] * a.head_w[2 * f + 1];
           }
         }
-      f0 += __shfl_xor(f0, 32, 64);
-      f1 += __shfl_xor(f1, 32, 64);
+      f0 = xor32_sum(f0);
+      f1 = xor32_sum(f1);
       if (h == 0) pw[rb * 32 + lr] = make_float2(f0, f1);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
