@@ -127,32 +127,49 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
 #pragma unroll
   for (int j = 0; j < NB; ++j) dW[j] = f32x16{};
 
+  // x (layer input, saved in BF16) and g (gradient of the sub-layer output) of block gb, lane ->
+  // row, values -> features 32 ib + tile_idx(r, h); loaded one tile ahead, so that the
+  // latency of the loads is covered by the previous tile's gradient phase
+  bf16x8 xn[NB][ST];
+  float4 gn[NB][4];
+  auto fetch = [&](int64_t tl) {
+    const int64_t g = 4 * tl + bw;
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib) {
+      if (tl < ntile && g < nblk) {
+        const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_x) + ((g * NB + ib) * 64 + lane) * 16;
+        xn[ib][0] = ld8(xs);
+        xn[ib][1] = ld8(xs + 8);
+        const float4* gs = reinterpret_cast<const float4*>(a.g_in + ((g * NB + ib) * 64 + lane) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gn[ib][q] = gs[q];
+      } else {
+        xn[ib][0] = xn[ib][1] = bf16x8{};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gn[ib][q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+  };
+  fetch(blockIdx.x);
+
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     // ================= block phase: head block hb of block gb
     const int64_t gb = 4 * tile + bw;
     const bool valid = gb < nblk;
     __bf16* S = stg + bw * NSTAGE * MAT;
-    // x (layer input, saved in BF16) and g (gradient of the sub-layer output) of the block as
-    // BF16 operands, lane -> row, values -> features 32 ib + tile_idx(8 s + t, h)
+    // the block's x and g as BF16 operands (values tile_idx(8 s + t, h))
     bf16x8 xo[NB][ST], go[NB][ST];
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) {
-      if (valid) {
-        const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_x) + ((gb * NB + ib) * 64 + lane) * 16;
-        xo[ib][0] = ld8(xs);
-        xo[ib][1] = ld8(xs + 8);
-        const float4* gs = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + ib) * 64 + lane) * 16);
-        f32x16 gr;
+      f32x16 gr;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 v = gs[q];
-          gr[4 * q] = v.x; gr[4 * q + 1] = v.y; gr[4 * q + 2] = v.z; gr[4 * q + 3] = v.w;
-        }
-        go[ib][0] = op8(gr, 0);
-        go[ib][1] = op8(gr, 1);
-      } else {
-        xo[ib][0] = xo[ib][1] = go[ib][0] = go[ib][1] = bf16x8{};
+      for (int q = 0; q < 4; ++q) {
+        gr[4 * q] = gn[ib][q].x; gr[4 * q + 1] = gn[ib][q].y; gr[4 * q + 2] = gn[ib][q].z; gr[4 * q + 3] = gn[ib][q].w;
       }
+      xo[ib][0] = xn[ib][0];
+      xo[ib][1] = xn[ib][1];
+      go[ib][0] = op8(gr, 0);
+      go[ib][1] = op8(gr, 1);
     }
     // the wave of head block 0 stages x, the other g
 #pragma unroll
@@ -305,6 +322,8 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     if (hb == 0 && valid) add_dx(a.g_in);
     __syncthreads();  // staging complete; head block 0's dx terms written
     if (hb == 1 && valid) add_dx(a.g_out);
+    // issued after the dx loads, which would otherwise wait behind these in the in-order load counter
+    fetch(tile + gridDim.x);
 
     // ================= gradient phase: wave w adds the tile's rows into its weight gradient rows
     {

@@ -157,17 +157,42 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   // staging role of this thread: block sb of the tile, feature block sob, lane sl
   const int sb = t >> 7, sob = (t >> 6) & 1, sl = lane, srow = 32 * sb + (sl & 31), sh = sl >> 5;
 
+  // x and (when it comes from memory) g of this thread's staging role, loaded one tile
+  // ahead so that the previous tile's phases cover the latency of the loads
+  bf16x8 xn[2];
+  float4 gn[4];
+  auto fetch = [&](int64_t tl) {
+    const int64_t g = 2 * tl + sb;
+    if (tl < ntile && g < nblk) {
+      const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_mid) + ((g * NB + sob) * 64 + sl) * 16;
+      xn[0] = ld8(xs);
+      xn[1] = ld8(xs + 8);
+      if (a.g_in) {
+        const float4* gs = reinterpret_cast<const float4*>(a.g_in + ((g * NB + sob) * 64 + sl) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gn[q] = gs[q];
+      }
+    }
+  };
+  fetch(blockIdx.x);
+
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     // ---- 1. stage x and g of the tile (wave = role (block sb, feature block sob))
     {
       const int64_t gb = 2 * tile + sb;
       bf16x8 xo[2], go[2];
       if (gb < nblk) {
-        const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_mid) + ((gb * NB + sob) * 64 + sl) * 16;
-        xo[0] = ld8(xs);
-        xo[1] = ld8(xs + 8);
+        xo[0] = xn[0];
+        xo[1] = xn[1];
         float g[16];
-        grad_tile<NB>(a, rm, E, gb, sob, sl, g);
+        if (a.g_in) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            g[4 * q] = gn[q].x; g[4 * q + 1] = gn[q].y; g[4 * q + 2] = gn[q].z; g[4 * q + 3] = gn[q].w;
+          }
+        } else {
+          grad_tile<NB>(a, rm, E, gb, sob, sl, g);
+        }
 #pragma unroll
         for (int r = 0; r < 16; ++r) db2[r] += g[r];
 #pragma unroll
@@ -192,6 +217,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
       }
     }
     __syncthreads();
+    fetch(tile + gridDim.x);
 
     // ---- 2. hidden units of this wave: u, dh, du; dW1, dW2, db1; du to LDS
 #pragma unroll
