@@ -39,8 +39,13 @@ namespace tdo {
 
 namespace {
 
-constexpr int FS = 40;               // row stride (bf16) of a staged [feature][row] matrix: conflict-free 16-byte reads
+constexpr int FS = 32;               // row stride (bf16) of a staged [feature][row] matrix (64 bytes)
 constexpr int MAT = 64 * FS;         // one staged matrix
+// Element offset of the 16-byte chunk c (rows 8c .. 8c+7 of the position order) of feature
+// f in a staged matrix.  The chunks of a feature are permuted by an XOR of bits of f so that
+// the 8 or 16 consecutive lanes of one 16-byte LDS access phase (consecutive features, same
+// c) fall on distinct banks without padding the rows.
+__device__ __forceinline__ int soff(int f, int c) { return f * FS + 8 * (c ^ (((f >> 1) ^ (f >> 3)) & 3)); }
 enum { SX = 0, SG = 1, SQ = 2, SK = 3, SV = 4, SO = 5, NSTAGE = 6 };
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
@@ -68,6 +73,13 @@ __device__ __forceinline__ bf16x8 op8(const f32x16& v, int s) {
 __device__ __forceinline__ f32x16 transpose_mfma(const bf16x8& x0, const bf16x8& x1, const bf16x8 (&eye)[2]) {
   return mfma16(x1, eye[1], mfma16(x0, eye[0], f32x16{}));
 }
+// Workgroup barrier ordering LDS only: global loads (the next tile's prefetch) and stores
+// stay in flight across it.
+__device__ __forceinline__ void barrier_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 // R-layout tile (lane -> row, values -> features f0 + tile_idx(r, h)), given as its two
 // BF16 operands, into a staged [feature][row position] matrix: transposed by MFMA, then
 // two 16-byte writes per lane.
@@ -75,19 +87,21 @@ __device__ __forceinline__ void stage_ops(__bf16* m, int f0, const bf16x8& o0, c
                                           const bf16x8 (&eye)[2], int lr, int h) {
   const f32x16 t = transpose_mfma(o0, o1, eye);  // lane -> feature f0 + lr, values -> rows
 #pragma unroll
-  for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(m + (f0 + lr) * FS + 16 * s + 8 * h) = op8(t, s);
+  for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(m + soff(f0 + lr, 2 * s + h)) = op8(t, s);
 }
 
 }  // namespace
 
-template <int DH>
+template <int DH, bool MASKED>
 __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
   constexpr int D = 64, NB = 2, ST = 2, HPB = 32 / DH;
   extern __shared__ __align__(16) char smem[];
   __bf16* Wl = reinterpret_cast<__bf16*>(smem);      // Wq, Wk, Wv, W_O^T fragments [4][D*D]
   __bf16* stg = Wl + 4 * D * D;                       // [4 blocks][NSTAGE][MAT]
+  float4* xch = reinterpret_cast<float4*>(stg + 4 * NSTAGE * MAT);  // [4 blocks][NB][4][64]: g + head block 0's dx terms
 
-  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31, w = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform (scalar branches below)
   const int bw = w & 3, hb = w >> 2;  // block of the tile, head block
   {
     const int4* sf = reinterpret_cast<const int4*>(a.wf);
@@ -107,7 +121,6 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
   const int64_t nblk = 2 * ((E + cpb - 1) / cpb);
   const int64_t ntile = (nblk + 3) / 4;
   const float sc = a.score_scale, isd = a.inv_sqrt_dh;
-  const bool masked = a.masked != 0;
   // permutation operands of transpose_mfma: eye[s][t] = [tile_idx(8 s + t, h) == lr]
   bf16x8 eye[2];
 #pragma unroll
@@ -237,7 +250,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       // query-major tiles: lane -> query lr, values -> keys tile_idx(r, h)
       f32x16 sq = PBF16::scores_packed<DH>(KRp[j], QRp[j], f32x16{});
       f32x16 dpq = PBF16::scores_packed<DH>(VRp[j], ORp[j], f32x16{});
-      if (masked) {
+      if constexpr (MASKED) {  // a compile-time choice keeps the head loop one scheduling region
 #pragma unroll
         for (int r = 0; r < 16; ++r)
           if (!((okbits >> r) & 1u)) sq[r] = -INFINITY;
@@ -292,37 +305,53 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     stage_ops(S + SK * MAT, 32 * hb, dk[0], dk[1], eye, lr, h);
     stage_ops(S + SV * MAT, 32 * hb, dv[0], dv[1], eye, lr, h);
 #pragma unroll
-    for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + (32 * hb + lr) * FS + 16 * s + 8 * h) = op8(AOF, s);
-    // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T: the terms of head block hb added to src (g for
-    // head block 0; for head block 1 what head block 0 wrote, each lane rereading only
-    // what the other wave's same lane wrote)
-    auto add_dx = [&](const float* src) {
+    for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + soff(32 * hb + lr, 2 * s + h)) = op8(AOF, s);
+    // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T.  The wave of head block 0 adds its terms to g and
+    // leaves the sum in LDS; after the barrier the wave of head block 1 adds its terms and
+    // writes dx (lane l of both waves holds the same rows and features).  The products start
+    // from zero and the loaded part is added last, so that its load overlaps them.
+    auto dx_terms = [&](int ob) {
+      f32x16 acc = {};
+      const int voff = (hb * ST * 64 + lane) * 16;  // fragment ((ob NB + hb) ST + s) of each matrix
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+        const int so = (ob * NB * ST + s) * 64 * 16;
+        acc = mfma16(buf_ld8(WT, voff, so), dq[s], acc);
+        acc = mfma16(buf_ld8(WT, voff, so + D * D * 2), dk[s], acc);
+        acc = mfma16(buf_ld8(WT, voff, so + 2 * D * D * 2), dv[s], acc);
+      }
+      return acc;
+    };
+    float4* X = xch + bw * NB * 4 * 64;
+    if (hb == 0 && valid) {
+      float4 sv[NB][4];
+#pragma unroll
+      for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sv[ob][q] = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + ob) * 64 + lane) * 16)[q];
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob) {
-        f32x16 acc;
-        const float4* sp = reinterpret_cast<const float4*>(src + ((gb * NB + ob) * 64 + lane) * 16);
+        const f32x16 acc = dx_terms(ob);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 v = sp[q];
-          acc[4 * q] = v.x; acc[4 * q + 1] = v.y; acc[4 * q + 2] = v.z; acc[4 * q + 3] = v.w;
-        }
-        const int voff = (hb * ST * 64 + lane) * 16;  // fragment ((ob NB + hb) ST + s) of each matrix
+        for (int q = 0; q < 4; ++q)
+          X[(ob * 4 + q) * 64 + lane] = make_float4(sv[ob][q].x + acc[4 * q], sv[ob][q].y + acc[4 * q + 1],
+                                                     sv[ob][q].z + acc[4 * q + 2], sv[ob][q].w + acc[4 * q + 3]);
+      }
+    }
+    barrier_lds();  // staging and head block 0's part of dx in LDS
+    if (hb == 1 && valid) {
 #pragma unroll
-        for (int s = 0; s < ST; ++s) {
-          const int so = (ob * NB * ST + s) * 64 * 16;
-          acc = mfma16(buf_ld8(WT, voff, so), dq[s], acc);
-          acc = mfma16(buf_ld8(WT, voff, so + D * D * 2), dk[s], acc);
-          acc = mfma16(buf_ld8(WT, voff, so + 2 * D * D * 2), dv[s], acc);
-        }
+      for (int ob = 0; ob < NB; ++ob) {
+        const f32x16 acc = dx_terms(ob);
         float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + ob) * 64 + lane) * 16);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+        for (int q = 0; q < 4; ++q) {
+          const float4 v = X[(ob * 4 + q) * 64 + lane];
+          dst[q] = make_float4(v.x + acc[4 * q], v.y + acc[4 * q + 1], v.z + acc[4 * q + 2], v.w + acc[4 * q + 3]);
+        }
       }
-    };
-    if (hb == 0 && valid) add_dx(a.g_in);
-    __syncthreads();  // staging complete; head block 0's dx terms written
-    if (hb == 1 && valid) add_dx(a.g_out);
-    // issued after the dx loads, which would otherwise wait behind these in the in-order load counter
+    }
+    // issued after the dx step, whose loads would otherwise wait behind these in the in-order load counter
     fetch(tile + gridDim.x);
 
     // ================= gradient phase: wave w adds the tile's rows into its weight gradient rows
@@ -335,16 +364,16 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         const __bf16* B = stg + (b * NSTAGE + bm) * MAT;
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
-          const bf16x8 av = ld8(A + (32 * hb + lr) * FS + 16 * s + 8 * h);
+          const bf16x8 av = ld8(A + soff(32 * hb + lr, 2 * s + h));
           bf16x8 bv[NB];
 #pragma unroll
-          for (int j = 0; j < NB; ++j) bv[j] = ld8(B + (32 * j + lr) * FS + 16 * s + 8 * h);
+          for (int j = 0; j < NB; ++j) bv[j] = ld8(B + soff(32 * j + lr, 2 * s + h));
 #pragma unroll
           for (int j = 0; j < NB; ++j) dW[j] = mfma16(av, bv[j], dW[j]);
         }
       }
     }
-    __syncthreads();
+    barrier_lds();  // staging read before the next tile overwrites it
   }
 
   float* part = a.partial + (int64_t)blockIdx.x * 4 * D * D + (int64_t)bw * D * D;
@@ -355,14 +384,14 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
 }
 
 size_t bwd_attn_bf16_lds() {
-  return (size_t)(4 * 64 * 64 + 4 * NSTAGE * MAT) * sizeof(__bf16);
+  return (size_t)(4 * 64 * 64 + 4 * NSTAGE * MAT) * sizeof(__bf16) + 4 * 2 * 64 * 16 * sizeof(float);
 }
 
 bool bwd_attn_bf16_supported(int d, int D, int DH, bool span) { return d == 64 && D == 64 && !span && (DH == 8 || DH == 16); }
 
 int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t st) {
   const size_t lds = bwd_attn_bf16_lds();
-  // the second head block's wave rereads the output written by the first
+  // written for distinct input and output gradient buffers
   TDO_CHECK(a.g_in != a.g_out, TDO_EINVAL, "BF16 attention backward cannot run in place");
   auto go = [&](auto kern) -> int32_t {
     TDO_TRY(allow_full_lds((const void*)kern));
@@ -370,8 +399,8 @@ int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t s
     TDO_HIP(hipGetLastError());
     return TDO_OK;
   };
-  if (DH == 8) return go(k_bwd_attn_bf16<8>);
-  if (DH == 16) return go(k_bwd_attn_bf16<16>);
+  if (DH == 8) return a.masked ? go(k_bwd_attn_bf16<8, true>) : go(k_bwd_attn_bf16<8, false>);
+  if (DH == 16) return a.masked ? go(k_bwd_attn_bf16<16, true>) : go(k_bwd_attn_bf16<16, false>);
   return set_error(TDO_EUNSUPPORTED, "BF16 attention backward: head width %d", DH);
 }
 
