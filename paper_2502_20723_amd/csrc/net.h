@@ -188,6 +188,34 @@ __device__ __forceinline__ float xor32_max(float x) {
   return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 
+// Bounded global access through a buffer resource over [p, p + bytes): loads outside it
+// return 0 and stores outside it are dropped by the hardware.  A wave can then keep one
+// unconditional sequence of memory operations (bytes = 0 disables them): the loads and
+// stores of a wave retire in order on one counter, and an access under a branch makes the
+// compiler wait for every outstanding one at the next use of a load issued before it.
+// p must be wave-uniform.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ bf16x8 rld8(__amdgpu_buffer_rsrc_t r, int voff, int soff = 0) {
+  return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ float4 rld4(__amdgpu_buffer_rsrc_t r, int voff) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+}
+__device__ __forceinline__ void rst4(__amdgpu_buffer_rsrc_t r, int voff, float4 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, voff, 0, 0);
+}
+
+// Workgroup barrier that orders LDS accesses only: global loads (a prefetch of the next
+// tile) and stores stay in flight across it, where __syncthreads would wait for them.
+__device__ __forceinline__ void barrier_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Exact ReLU of the feed-forward sub-layer.
 __device__ __forceinline__ float relu(float x) { return x > 0.f ? x : 0.f; }
 

@@ -49,13 +49,6 @@ __device__ __forceinline__ int soff(int f, int c) { return f * FS + 8 * (c ^ (((
 enum { SX = 0, SG = 1, SQ = 2, SK = 3, SV = 4, SO = 5, NSTAGE = 6 };
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
-// 16-byte load through a buffer resource: one lane offset (VGPR) shared by all
-// fragments and a uniform offset per fragment, instead of one 64-bit address per
-// fragment kept live across the tile loop.  Reads past the resource's size return 0.
-__device__ __forceinline__ bf16x8 buf_ld8(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
-}
-constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer access on gfx9-class devices
 __device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
@@ -72,13 +65,6 @@ __device__ __forceinline__ bf16x8 op8(const f32x16& v, int s) {
 // returned in the MFMA result layout.  The BF16 inputs pass through unchanged.
 __device__ __forceinline__ f32x16 transpose_mfma(const bf16x8& x0, const bf16x8& x1, const bf16x8 (&eye)[2]) {
   return mfma16(x1, eye[1], mfma16(x0, eye[0], f32x16{}));
-}
-// Workgroup barrier ordering LDS only: global loads (the next tile's prefetch) and stores
-// stay in flight across it.
-__device__ __forceinline__ void barrier_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 // R-layout tile (lane -> row, values -> features f0 + tile_idx(r, h)), given as its two
 // BF16 operands, into a staged [feature][row position] matrix: transposed by MFMA, then
@@ -111,9 +97,10 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     for (int i = t; i < D * D / 8; i += 512) dl[3 * D * D / 8 + i] = sb[3 * D * D / 8 + i];
   }
   const __bf16 *Wq = Wl, *Wk = Wl + D * D, *Wv = Wl + 2 * D * D, *WoT = Wl + 3 * D * D;
-  // Wq^T, Wk^T, Wv^T fragments [3][D*D] BF16 in global memory (L2-resident)
-  const __amdgpu_buffer_rsrc_t WT = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(a.wb), (short)0,
-                                                                      3 * D * D * 2, RSRC_WORD3);
+  // Wq^T, Wk^T, Wv^T fragments [3][D*D] BF16 in global memory (L2-resident), read through a
+  // buffer resource: one lane offset shared by all fragments and a uniform offset per
+  // fragment, instead of one 64-bit address per fragment kept live across the tile loop
+  const __amdgpu_buffer_rsrc_t WT = rsrc(a.wb, 3 * D * D * 2);
   __syncthreads();
 
   const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
@@ -316,9 +303,9 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
         const int so = (ob * NB * ST + s) * 64 * 16;
-        acc = mfma16(buf_ld8(WT, voff, so), dq[s], acc);
-        acc = mfma16(buf_ld8(WT, voff, so + D * D * 2), dk[s], acc);
-        acc = mfma16(buf_ld8(WT, voff, so + 2 * D * D * 2), dv[s], acc);
+        acc = mfma16(rld8(WT, voff, so), dq[s], acc);
+        acc = mfma16(rld8(WT, voff, so + D * D * 2), dk[s], acc);
+        acc = mfma16(rld8(WT, voff, so + 2 * D * D * 2), dv[s], acc);
       }
       return acc;
     };

@@ -98,7 +98,9 @@ __device__ __forceinline__ void grad_tile(const BwdArgs& a, const RowMap& rm, in
   }
 }
 
-template <int M>
+// SEEDS: the last layer, whose incoming gradient is formed from the per-configuration seeds
+// (g_in NULL); otherwise g is read from g_in.
+template <int M, bool SEEDS>
 __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   constexpr int D = 64, NB = 2, HW = M / 4, HT = HW / 32, KS = M / 16, DUS = M + 8;
   static_assert(HT >= 1 && HT <= 2 && HW % 32 == 0, "hidden width 128 or 256");
@@ -110,8 +112,10 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   __bf16* DU = GT + D * XS;                       // [RT][DUS]  du, row-major, hidden units in perm16 order
   __bf16* W1s = DU + RT * DUS;                    // [D][DUS]   W1 (operand of dx = du W1^T), same order
   float* db2s = reinterpret_cast<float*>(W1s + D * DUS);  // [2 blocks of the tile][D]
+  float4* GF = reinterpret_cast<float4*>(db2s + 2 * D);   // [4 waves][4][64]: g in FP32 for the residual of dx
 
-  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31, w = t >> 6;
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
   const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
   const RowMap rm{a.n, a.cpb, a.span != 0};
   const int64_t nblk = a.span ? 4 * E : 2 * ((E + a.cpb - 1) / a.cpb);
@@ -155,26 +159,33 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   for (int r = 0; r < 16; ++r) db2[r] = 0.f;
 
   // staging role of this thread: block sb of the tile, feature block sob, lane sl
-  const int sb = t >> 7, sob = (t >> 6) & 1, sl = lane, srow = 32 * sb + (sl & 31), sh = sl >> 5;
+  const int sb = w >> 1, sob = w & 1, sl = lane, srow = 32 * sb + (sl & 31), sh = sl >> 5;
 
   // x and (when it comes from memory) g of this thread's staging role, loaded one tile
   // ahead so that the previous tile's phases cover the latency of the loads
   bf16x8 xn[2];
   float4 gn[4];
-  auto fetch = [&](int64_t tl) {
+  auto fetch = [&](int64_t tl) {  // zeros past the last block
     const int64_t g = 2 * tl + sb;
-    if (tl < ntile && g < nblk) {
-      const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_mid) + ((g * NB + sob) * 64 + sl) * 16;
-      xn[0] = ld8(xs);
-      xn[1] = ld8(xs + 8);
-      if (a.g_in) {
-        const float4* gs = reinterpret_cast<const float4*>(a.g_in + ((g * NB + sob) * 64 + sl) * 16);
+    const bool ok = tl < ntile && g < nblk;
+    const auto rx = rsrc(reinterpret_cast<const __bf16*>(a.save_mid) + (g * NB + sob) * 64 * 16, ok ? 64 * 16 * 2 : 0);
+    xn[0] = rld8(rx, sl * 32);
+    xn[1] = rld8(rx, sl * 32 + 16);
+    if constexpr (!SEEDS) {
+      const auto rg = rsrc(a.g_in + (g * NB + sob) * 64 * 16, ok ? 64 * 16 * 4 : 0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) gn[q] = gs[q];
-      }
+      for (int q = 0; q < 4; ++q) gn[q] = rld4(rg, sl * 64 + 16 * q);
     }
   };
   fetch(blockIdx.x);
+  {
+    // the same number of stores after the prefetch on the path into the loop as at the end of
+    // every tile (dropped: the resource is empty), so that the wait for the prefetch at the top
+    // of the loop need not cover the stores
+    const auto rz = rsrc(a.g_out, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rst4(rz, 16 * i, make_float4(0.f, 0.f, 0.f, 0.f));
+  }
 
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     // ---- 1. stage x and g of the tile (wave = role (block sb, feature block sob))
@@ -185,13 +196,13 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
         xo[0] = xn[0];
         xo[1] = xn[1];
         float g[16];
-        if (a.g_in) {
+        if constexpr (SEEDS) {
+          grad_tile<NB>(a, rm, E, gb, sob, sl, g);
+        } else {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             g[4 * q] = gn[q].x; g[4 * q + 1] = gn[q].y; g[4 * q + 2] = gn[q].z; g[4 * q + 3] = gn[q].w;
           }
-        } else {
-          grad_tile<NB>(a, rm, E, gb, sob, sl, g);
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) db2[r] += g[r];
@@ -199,6 +210,9 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
         for (int s = 0; s < 2; ++s)
 #pragma unroll
           for (int k = 0; k < 8; ++k) go[s][k] = (__bf16)g[8 * s + k];
+        // the same wave and lane form the dx tile (block sb, features sob) in phase 3
+#pragma unroll
+        for (int q = 0; q < 4; ++q) GF[(w * 4 + q) * 64 + lane] = make_float4(g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]);
       } else {
         xo[0] = xo[1] = go[0] = go[1] = bf16x8{};
       }
@@ -216,7 +230,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
         *reinterpret_cast<bf16x8*>(GT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = op8(gt, s);
       }
     }
-    __syncthreads();
+    barrier_lds();
     fetch(tile + gridDim.x);
 
     // ---- 2. hidden units of this wave: u, dh, du; dW1, dW2, db1; du to LDS
@@ -275,7 +289,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
           *reinterpret_cast<bf16x8*>(DU + (32 * rb + lr) * DUS + hid0 + 32 * nt + 16 * s + 8 * h) = op8(dut, s);
       }
     }
-    __syncthreads();
+    barrier_lds();
 
     // ---- 3. dx tile (rows of block rb3, features of block it3) = g + du W1^T
     {
@@ -284,17 +298,16 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
 #pragma unroll
       for (int s = 0; s < KS; ++s)  // A[m = in][k = hidden] = W1, B[k = hidden][n = row] = du
         acc = mfma16(ld8(W1s + (32 * it3 + lr) * DUS + 16 * s + 8 * h), ld8(DU + (32 * rb3 + lr) * DUS + 16 * s + 8 * h), acc);
-      if (gb < nblk) {
-        float g[16];
-        grad_tile<NB>(a, rm, E, gb, it3, lane, g);
-        float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + it3) * 64 + lane) * 16);
+      // stores issued by every wave (dropped past the last block): see the loop entry
+      const auto ro = rsrc(a.g_out + (gb * NB + it3) * 64 * 16, gb < nblk ? 64 * 16 * 4 : 0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          dst[q] = make_float4(acc[4 * q] + g[4 * q], acc[4 * q + 1] + g[4 * q + 1], acc[4 * q + 2] + g[4 * q + 2],
-                               acc[4 * q + 3] + g[4 * q + 3]);
+      for (int q = 0; q < 4; ++q) {
+        const float4 g = GF[(w * 4 + q) * 64 + lane];  // staged by this lane in phase 1
+        rst4(ro, lane * 64 + 16 * q,
+             make_float4(acc[4 * q] + g.x, acc[4 * q + 1] + g.y, acc[4 * q + 2] + g.z, acc[4 * q + 3] + g.w));
       }
     }
-    __syncthreads();
+    barrier_lds();
   }
 
   // ---- write this workgroup's gradients: dW1 [D][M], dW2 [M][D], db1 [M], db2 [D]
@@ -327,7 +340,8 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
 }
 
 size_t bwd_mlp_bf16_lds(int M) {
-  return (size_t)(2 * RT * XS + 2 * 64 * XS + (RT + 64) * (M + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float);
+  return (size_t)(2 * RT * XS + 2 * 64 * XS + (RT + 64) * (M + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float) +
+         4 * 4 * 64 * sizeof(float4);
 }
 
 bool bwd_mlp_bf16_supported(int d, int D, int M) { return d == 64 && D == 64 && (M == 128 || M == 256); }
@@ -340,9 +354,10 @@ int32_t launch_bwd_mlp_bf16(const BwdArgs& a, int blocks, hipStream_t st) {
     TDO_HIP(hipGetLastError());
     return TDO_OK;
   };
+  const bool seeds = a.g_in == nullptr;
   switch (a.M) {
-    case 128: return go(k_bwd_mlp_bf16<128>);
-    case 256: return go(k_bwd_mlp_bf16<256>);
+    case 128: return seeds ? go(k_bwd_mlp_bf16<128, true>) : go(k_bwd_mlp_bf16<128, false>);
+    case 256: return seeds ? go(k_bwd_mlp_bf16<256, true>) : go(k_bwd_mlp_bf16<256, false>);
     default: return set_error(TDO_EUNSUPPORTED, "BF16 feed-forward backward: mlp width %d", a.M);
   }
 }
