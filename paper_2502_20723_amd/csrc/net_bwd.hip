@@ -447,11 +447,17 @@ __global__ void __launch_bounds__(256) k_bwd_head(const void* __restrict__ save_
   for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
     for (int r = 0; r < 16; ++r) a0[ob][r] = a1[ob][r] = 0.0;
+  // no early exit for padding rows (their seeds are taken as 0: the forward wrote finite values
+  // for them, which then add exactly 0), so that two blocks' loads can be in flight at once
+#pragma unroll 2
   for (int64_t g = (int64_t)blockIdx.x * 4 + wave; g < nblk; g += (int64_t)gridDim.x * 4) {
     int64_t e; int pass, ric; bool valid;
     rm.at(g, lr, E, e, pass, ric, valid);
-    if (!valid) continue;
-    const float s0 = seeds[(e * 2 + pass) * 2] * inv_n, s1 = seeds[(e * 2 + pass) * 2 + 1] * inv_n;
+    float s0 = 0.f, s1 = 0.f;
+    if (valid) {
+      s0 = seeds[(e * 2 + pass) * 2] * inv_n;
+      s1 = seeds[(e * 2 + pass) * 2 + 1] * inv_n;
+    }
     if (h == 0) { c0 += s0; c1 += s1; }
 #pragma unroll
     for (int ob = 0; ob < NB; ++ob) {
@@ -598,11 +604,28 @@ __global__ void k_embed_params(const float* __restrict__ params, const double* _
 }
 
 // Sum nparts FP32 partials of length len in index order into FP64 out[i] (+=).
-__global__ void k_reduce_partials(const float* __restrict__ part, int nparts, int64_t len, double* __restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += (double)part[(int64_t)p * len + i];
-    out[i] += s;
+// A workgroup of 256 threads sums EPB consecutive elements over all nparts partials:
+// G = 256 / EPB groups of threads each take every G-th partial, and the group sums are
+// added in a fixed order (deterministic), so that enough loads are in flight per element.
+template <int EPB>
+__global__ void __launch_bounds__(256) k_reduce_partials(const float* __restrict__ part, int nparts, int64_t len,
+                                                         double* __restrict__ out) {
+  constexpr int G = 256 / EPB;
+  __shared__ double sh[G][EPB];
+  const int j = threadIdx.x % EPB, g = threadIdx.x / EPB;
+  const int64_t i = (int64_t)blockIdx.x * EPB + j;
+  double s = 0.0;
+  if (i < len) {
+#pragma unroll 8
+    for (int p = g; p < nparts; p += G) s += (double)part[(int64_t)p * len + i];
+  }
+  sh[g][j] = s;
+  __syncthreads();
+  if (g == 0 && i < len) {
+    double t = sh[0][j];
+#pragma unroll
+    for (int q = 1; q < G; ++q) t += sh[q][j];
+    out[i] += t;
   }
 }
 
@@ -704,8 +727,12 @@ int32_t launch_embed_params(const float* params, const double* dT, int d, int D,
 }
 
 int32_t launch_reduce_partials(const float* part, int nparts, int64_t len, double* out, hipStream_t st) {
-  const int blocks = (int)std::min<int64_t>(ceil_div(len, 256), 2048);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(blocks), dim3(256), 0, st, part, nparts, len, out);
+  if (len <= 0) return TDO_OK;
+  if (ceil_div(len, 64) >= 256) {  // enough workgroups with 4 groups of partials
+    hipLaunchKernelGGL(k_reduce_partials<64>, dim3((unsigned)ceil_div(len, 64)), dim3(256), 0, st, part, nparts, len, out);
+  } else {
+    hipLaunchKernelGGL(k_reduce_partials<16>, dim3((unsigned)ceil_div(len, 16)), dim3(256), 0, st, part, nparts, len, out);
+  }
   TDO_HIP(hipGetLastError());
   return TDO_OK;
 }

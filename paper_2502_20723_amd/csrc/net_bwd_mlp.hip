@@ -66,38 +66,6 @@ __device__ __forceinline__ f32x16 transpose_mfma(const bf16x8& x0, const bf16x8&
 
 }  // namespace
 
-// Gradient entering the sub-layer for (block gb, feature block ob, lane l):
-// 16 values, features 32 ob + tile_idx(r, l/32) of row l%32 of the block.
-template <int NB>
-__device__ __forceinline__ void grad_tile(const BwdArgs& a, const RowMap& rm, int64_t E, int64_t gb, int ob, int l,
-                                          float (&g)[16]) {
-  if (a.g_in) {
-    const float4* p = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + ob) * 64 + l) * 16);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float4 t = p[q];
-      g[4 * q] = t.x; g[4 * q + 1] = t.y; g[4 * q + 2] = t.z; g[4 * q + 3] = t.w;
-    }
-    return;
-  }
-  // last layer: g = (dF0 head_w[:,0] + dF1 head_w[:,1]) / n from the pooled head
-  int64_t e;
-  int pass, ric;
-  bool valid;
-  rm.at(gb, l & 31, E, e, pass, ric, valid);
-  float s0 = 0.f, s1 = 0.f;
-  if (valid) {
-    s0 = a.seeds[(e * 2 + pass) * 2] / (float)a.n;
-    s1 = a.seeds[(e * 2 + pass) * 2 + 1] / (float)a.n;
-  }
-  const int h = l >> 5;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int f = 32 * ob + tile_idx(r, h);
-    g[r] = f < a.d_real ? s0 * a.head_w[2 * f] + s1 * a.head_w[2 * f + 1] : 0.f;
-  }
-}
-
 // SEEDS: the last layer, whose incoming gradient is formed from the per-configuration seeds
 // (g_in NULL); otherwise g is read from g_in.
 template <int M, bool SEEDS>
@@ -113,6 +81,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   __bf16* W1s = DU + RT * DUS;                    // [D][DUS]   W1 (operand of dx = du W1^T), same order
   float* db2s = reinterpret_cast<float*>(W1s + D * DUS);  // [2 blocks of the tile][D]
   float4* GF = reinterpret_cast<float4*>(db2s + 2 * D);   // [4 waves][4][64]: g in FP32 for the residual of dx
+  float2* hws = reinterpret_cast<float2*>(GF + 4 * 4 * 64);  // SEEDS: head weight pairs [D], zero past d
 
   const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
@@ -142,7 +111,9 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
     for (int t2 = 0; t2 < 8; ++t2) eye[s2][t2] = (__bf16)(tile_idx(8 * s2 + t2, h) == lr ? 1.0f : 0.0f);
-  __syncthreads();  // W1s initialised before any use
+  if constexpr (SEEDS)
+    for (int i = t; i < D; i += 256) hws[i] = i < a.d_real ? make_float2(a.head_w[2 * i], a.head_w[2 * i + 1]) : make_float2(0.f, 0.f);
+  __syncthreads();  // W1s (and the head weights) initialised before any use
   float bias[HT];
 #pragma unroll
   for (int nt = 0; nt < HT; ++nt) bias[nt] = a.b1[hid0 + 32 * nt + lr];
@@ -197,7 +168,21 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
         xo[1] = xn[1];
         float g[16];
         if constexpr (SEEDS) {
-          grad_tile<NB>(a, rm, E, gb, sob, sl, g);
+          // g = (dF0 head_w[:, 0] + dF1 head_w[:, 1]) / n from the pooled head (per row's configuration-pass)
+          int64_t e;
+          int pass, ric;
+          bool rv;
+          rm.at(gb, sl & 31, E, e, pass, ric, rv);
+          float s0 = 0.f, s1 = 0.f;
+          if (rv) {
+            s0 = a.seeds[(e * 2 + pass) * 2] / (float)a.n;
+            s1 = a.seeds[(e * 2 + pass) * 2 + 1] / (float)a.n;
+          }
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const float2 hw = hws[32 * sob + tile_idx(r, sh)];
+            g[r] = s0 * hw.x + s1 * hw.y;
+          }
         } else {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -341,7 +326,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
 
 size_t bwd_mlp_bf16_lds(int M) {
   return (size_t)(2 * RT * XS + 2 * 64 * XS + (RT + 64) * (M + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float) +
-         4 * 4 * 64 * sizeof(float4);
+         4 * 4 * 64 * sizeof(float4) + 64 * sizeof(float2);
 }
 
 bool bwd_mlp_bf16_supported(int d, int D, int M) { return d == 64 && D == 64 && (M == 128 || M == 256); }

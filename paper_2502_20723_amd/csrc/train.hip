@@ -183,8 +183,9 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
                           gt + pp.off_head_b, st));
   // table gradient accumulated over every call of this entry point; the chain rule into the
   // convolution parameters (linear in it) runs once at the end (finish_backward)
-  TDO_TRY(launch_embed_scatter(D, bb.ga, ecfg, E_dev, E, np.n, np.cpb, np.span, bb.partial, bb.nparts, st));
-  TDO_TRY(launch_reduce_partials(bb.partial, 4 * bb.nparts, 64LL * D, bb.dT_acc, st));
+  // two workgroups per CU (each wave a partial): the second one's waves hide the first's latencies
+  TDO_TRY(launch_embed_scatter(D, bb.ga, ecfg, E_dev, E, np.n, np.cpb, np.span, bb.partial, 2 * bb.nparts, st));
+  TDO_TRY(launch_reduce_partials(bb.partial, 8 * bb.nparts, 64LL * D, bb.dT_acc, st));
   return TDO_OK;
 }
 
@@ -208,7 +209,8 @@ int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, T
   t->mlp_acc = ar.take<double>(mlen);
   t->attn_acc = ar.take<double>(4LL * np.D * np.D);
   t->dT_acc = ar.take<double>(64LL * np.D);
-  const int64_t maxlen = std::max<int64_t>(std::max<int64_t>(mlen, 4LL * np.D * np.D), 4 * 64LL * np.D);
+  // per CU: the feed-forward or attention weight partials, or 8 wave partials of the table gradient
+  const int64_t maxlen = std::max<int64_t>(std::max<int64_t>(mlen, 4LL * np.D * np.D), 8 * 64LL * np.D);
   t->partial = ar.take<float>((size_t)c.num_cus * maxlen);
   const size_t fixed = ar.used + 64 * 256;  // includes the per-sample L buffer
   const int save = np.bf16 ? 2 : 4;
