@@ -201,6 +201,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, uint32_t b
 __device__ __forceinline__ bf16x8 rld8(__amdgpu_buffer_rsrc_t r, int voff, int soff = 0) {
   return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
+__device__ __forceinline__ float2 rld2(__amdgpu_buffer_rsrc_t r, int voff) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+}
 __device__ __forceinline__ float4 rld4(__amdgpu_buffer_rsrc_t r, int voff) {
   return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
 }

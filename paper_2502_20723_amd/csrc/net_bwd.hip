@@ -551,10 +551,14 @@ __global__ void __launch_bounds__(256) k_embed_onehot(const float* __restrict__ 
 
 // Chain rule from the table gradient dT[64][D] (FP64) into the convolution
 // parameters; one workgroup, FP64 (recomputes the table's pre-activations).
-__global__ void k_embed_params(const float* __restrict__ params, const double* __restrict__ dT, int d, int D,
-                               double* __restrict__ grad) {
+__global__ void __launch_bounds__(64) k_embed_params(const float* __restrict__ params, const double* __restrict__ dT,
+                                                     int d, int D, double* __restrict__ grad) {
   // grad layout: conv1_w [2][2][d], conv1_b [d], conv2_w [2][d][d], conv2_b [d]
-  __shared__ double ea[64], eb[64], ga[64], gb[64], gpre[64];
+  extern __shared__ __align__(16) char smem[];
+  double* gw2 = reinterpret_cast<double*>(smem);  // conv2_w gradient [2][d][d], accumulated over the codes
+  double* ea = gw2 + 2 * d * d;                   // [64] each
+  double *eb = ea + 64, *ga = eb + 64, *gb = ga + 64, *gpre = gb + 64;
+  float* w2s = reinterpret_cast<float*>(gpre + 64);  // conv2_w [2][d][d]
   const float* w1 = params;
   const float* b1 = params + 4 * d;
   const float* w2 = b1 + d;
@@ -567,6 +571,11 @@ __global__ void k_embed_params(const float* __restrict__ params, const double* _
   auto phi = [](double u) { return 0.5 * u * (1.0 + erf(u * 0.7071067811865476)); };
   auto dphi = [](double u) { return 0.5 * (1.0 + erf(u * 0.7071067811865476)) + u * 0.3989422804014327 * exp(-0.5 * u * u); };
   const int t = threadIdx.x;
+  for (int i = t; i < 2 * d * d; i += 64) {
+    gw2[i] = 0.0;
+    w2s[i] = w2[i];
+  }
+  __syncthreads();
   for (int code = 0; code < 64; ++code) {
     const int t0 = code & 3, t1 = (code >> 2) & 3, t2 = (code >> 4) & 3;
     double pa = 0, pb = 0;
@@ -579,18 +588,18 @@ __global__ void k_embed_params(const float* __restrict__ params, const double* _
     __syncthreads();
     if (t < d) {  // output feature o = t: pre-activation and its gradient
       double acc = b2[t];
-      for (int c = 0; c < d; ++c) acc += ea[c] * w2[c * d + t] + eb[c] * w2[d * d + c * d + t];
+      for (int c = 0; c < d; ++c) acc += ea[c] * w2s[c * d + t] + eb[c] * w2s[d * d + c * d + t];
       gpre[t] = dT[code * D + t] * dphi(acc);
     }
     __syncthreads();
     if (t < d) {
       g_b2[t] += gpre[t];
       for (int o = 0; o < d; ++o) {  // thread t = input channel c
-        g_w2[t * d + o] += ea[t] * gpre[o];
-        g_w2[d * d + t * d + o] += eb[t] * gpre[o];
+        gw2[t * d + o] += ea[t] * gpre[o];
+        gw2[d * d + t * d + o] += eb[t] * gpre[o];
       }
       double da = 0, db = 0;
-      for (int o = 0; o < d; ++o) { da += w2[t * d + o] * gpre[o]; db += w2[d * d + t * d + o] * gpre[o]; }
+      for (int o = 0; o < d; ++o) { da += w2s[t * d + o] * gpre[o]; db += w2s[d * d + t * d + o] * gpre[o]; }
       ga[t] = da * dphi(pa);
       gb[t] = db * dphi(pb);
       g_b1[t] += ga[t] + gb[t];
@@ -601,6 +610,7 @@ __global__ void k_embed_params(const float* __restrict__ params, const double* _
     }
     __syncthreads();
   }
+  for (int i = t; i < 2 * d * d; i += 64) g_w2[i] += gw2[i];
 }
 
 // Sum nparts FP32 partials of length len in index order into FP64 out[i] (+=).
@@ -721,7 +731,10 @@ int32_t launch_embed_scatter(int D, const float* dx0, const uint64_t* ecfg, cons
 }
 
 int32_t launch_embed_params(const float* params, const double* dT, int d, int D, double* grad, hipStream_t st) {
-  hipLaunchKernelGGL(k_embed_params, dim3(1), dim3(64), 0, st, params, dT, d, D, grad);
+  TDO_CHECK(d <= 64, TDO_EUNSUPPORTED, "embedding chain rule: width %d > 64", d);
+  const size_t lds = (size_t)2 * d * d * (sizeof(double) + sizeof(float)) + 5 * 64 * sizeof(double);
+  TDO_TRY(allow_full_lds((const void*)k_embed_params));
+  hipLaunchKernelGGL(k_embed_params, dim3(1), dim3(64), lds, st, params, dT, d, D, grad);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
 }

@@ -136,6 +136,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   // ahead so that the previous tile's phases cover the latency of the loads
   bf16x8 xn[2];
   float4 gn[4];
+  float2 sn;  // SEEDS: (dF0, dF1) of this lane's row
   auto fetch = [&](int64_t tl) {  // zeros past the last block
     const int64_t g = 2 * tl + sb;
     const bool ok = tl < ntile && g < nblk;
@@ -146,6 +147,13 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
       const auto rg = rsrc(a.g_in + (g * NB + sob) * 64 * 16, ok ? 64 * 16 * 4 : 0);
 #pragma unroll
       for (int q = 0; q < 4; ++q) gn[q] = rld4(rg, sl * 64 + 16 * q);
+    } else {
+      int64_t e;
+      int pass, ric;
+      bool rv;
+      rm.at(ok ? g : 0, sl & 31, E, e, pass, ric, rv);
+      const auto rs = rsrc(a.seeds, ok ? (uint32_t)(E * 4 * sizeof(float)) : 0u);
+      sn = rld2(rs, rv ? (int)((e * 2 + pass) * 2 * sizeof(float)) : 0x7ffffff0);  // out of range: zeros
     }
   };
   fetch(blockIdx.x);
@@ -169,15 +177,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
         float g[16];
         if constexpr (SEEDS) {
           // g = (dF0 head_w[:, 0] + dF1 head_w[:, 1]) / n from the pooled head (per row's configuration-pass)
-          int64_t e;
-          int pass, ric;
-          bool rv;
-          rm.at(gb, sl & 31, E, e, pass, ric, rv);
-          float s0 = 0.f, s1 = 0.f;
-          if (rv) {
-            s0 = a.seeds[(e * 2 + pass) * 2] / (float)a.n;
-            s1 = a.seeds[(e * 2 + pass) * 2 + 1] / (float)a.n;
-          }
+          const float s0 = sn.x / (float)a.n, s1 = sn.y / (float)a.n;
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const float2 hw = hws[32 * sob + tile_idx(r, sh)];
