@@ -324,6 +324,240 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
   if (t < D) part[2 * D * M + M + t] = db2s[t] + db2s[D + t];
 }
 
+// Variant for m = 256 with 8 waves, two per SIMD (one wave's latencies overlap the
+// other's work).  Wave w owns hidden units [32 w, 32 w + 32): its weight operands and
+// gradients fit in half of a SIMD's registers.  Roles per tile (q = w mod 4: block q/2,
+// feature block q mod 2): waves 0-3 stage x, waves 4-7 stage g and keep it in FP32 for the
+// residual of dx.  The four 32x32 tiles of dx are split over the hidden units in halves:
+// wave q sums hidden [128, 256) and leaves its part in LDS; after a barrier wave q + 4,
+// which staged g of the same tile, adds hidden [0, 128), that part and the residual, and
+// writes dx.  Every cross-wave use of LDS is ordered by one of the three barriers of a tile.
+template <bool SEEDS>
+__global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
+  constexpr int M = 256, D = 64, NB = 2, DUS = M + 8;
+  extern __shared__ __align__(16) char smem[];
+  __bf16* XA = reinterpret_cast<__bf16*>(smem);  // [RT][XS]   x, row-major (features in perm16 order)
+  __bf16* XT = XA + RT * XS;                      // [D][XS]    x^T, rows in perm16 order
+  __bf16* GA = XT + D * XS;                       // [RT][XS]   g, row-major
+  __bf16* GT = GA + RT * XS;                      // [D][XS]    g^T
+  __bf16* DU = GT + D * XS;                       // [RT][DUS]  du, row-major, hidden units in perm16 order
+  __bf16* W1s = DU + RT * DUS;                    // [D][DUS]   W1 (operand of dx = du W1^T), same order
+  float* db2s = reinterpret_cast<float*>(W1s + D * DUS);     // [2 blocks of the tile][D]
+  float4* GF = reinterpret_cast<float4*>(db2s + 2 * D);      // [4 roles][4][64]: g in FP32
+  float4* XD = GF + 4 * 4 * 64;                              // [4 tiles][4][64]: dx over hidden [128, 256)
+  float2* hws = reinterpret_cast<float2*>(XD + 4 * 4 * 64);  // SEEDS: head weight pairs [D], zero past d
+
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform
+  const int q = w & 3, sb = q >> 1, sob = q & 1, srow = 32 * sb + lr;
+  const bool gw = w >= 4;  // stages g and finishes dx
+  const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
+  const RowMap rm{a.n, a.cpb, a.span != 0};
+  const int64_t nblk = a.span ? 4 * E : 2 * ((E + a.cpb - 1) / a.cpb);
+  const int64_t ntile = (nblk + 1) / 2;
+
+  // ---- weights of this wave, as BF16 MFMA operands (read once per launch)
+  const int hid = 32 * w + lr;  // hidden unit of this lane in (row x hidden) results
+  bf16x8 w1b[4], w2b[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int f = perm16(16 * s + 8 * h + k);  // order of XA, GA
+      w1b[s][k] = (__bf16)a.w1[f * M + hid];     // B[k = in][n = hidden] = W1[in][hidden]
+      w2b[s][k] = (__bf16)a.w2[hid * D + f];     // B[k = out][n = hidden] = W2[hidden][out]
+    }
+  for (int i = t; i < D * M; i += 512) W1s[(i / M) * DUS + perm16(i % M)] = (__bf16)a.w1[i];
+  if constexpr (SEEDS)
+    for (int i = t; i < D; i += 512) hws[i] = i < a.d_real ? make_float2(a.head_w[2 * i], a.head_w[2 * i + 1]) : make_float2(0.f, 0.f);
+  bf16x8 eye[2];  // permutation operands of transpose_mfma
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int t2 = 0; t2 < 8; ++t2) eye[s2][t2] = (__bf16)(tile_idx(8 * s2 + t2, h) == lr ? 1.0f : 0.0f);
+  __syncthreads();  // W1s and the head weights initialised before any use
+  const float bias = a.b1[hid];
+
+  f32x16 dW1[NB], dW2[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) dW1[i] = dW2[i] = f32x16{};
+  float db1 = 0.f, db2[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) db2[r] = 0.f;
+
+  // x (waves 0-3) or g (waves 4-7) of this wave's role, loaded one tile ahead (zeros past the end)
+  bf16x8 xn[2];
+  float4 gn[4];
+  float2 sn;
+  auto fetch = [&](int64_t tl) {
+    const int64_t g = 2 * tl + sb;
+    const bool ok = tl < ntile && g < nblk;
+    if (!gw) {
+      const auto rx = rsrc(reinterpret_cast<const __bf16*>(a.save_mid) + (g * NB + sob) * 64 * 16, ok ? 64 * 16 * 2 : 0);
+      xn[0] = rld8(rx, lane * 32);
+      xn[1] = rld8(rx, lane * 32 + 16);
+    } else if constexpr (!SEEDS) {
+      const auto rg = rsrc(a.g_in + (g * NB + sob) * 64 * 16, ok ? 64 * 16 * 4 : 0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) gn[k] = rld4(rg, lane * 64 + 16 * k);
+    } else {
+      int64_t e;
+      int pass, ric;
+      bool rv;
+      rm.at(ok ? g : 0, lr, E, e, pass, ric, rv);
+      const auto rs = rsrc(a.seeds, ok ? (uint32_t)(E * 4 * sizeof(float)) : 0u);
+      sn = rld2(rs, rv ? (int)((e * 2 + pass) * 2 * sizeof(float)) : 0x7ffffff0);  // out of range: zeros
+    }
+  };
+  fetch(blockIdx.x);
+  {
+    // the same stores after the prefetch on the path into the loop as at the end of every tile
+    // (dropped: empty resource), so that the wait for the prefetch need not cover the stores
+    const auto rz = rsrc(a.g_out, 0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) rst4(rz, 16 * k, make_float4(0.f, 0.f, 0.f, 0.f));
+  }
+
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t gb = 2 * tile + sb;  // block of this wave's role
+    // ---- 1. stage x (waves 0-3) or g (waves 4-7): row-major and transposed, 16-byte writes;
+    // value t of operand s is feature 32 sob + tile_idx(8 s + t, h), position 32 sob + 16 s + 8 h + t
+    if (!gw) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(XA + srow * XS + 32 * sob + 16 * s + 8 * h) = xn[s];
+      const f32x16 xt = transpose_mfma(xn[0], xn[1], eye);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(XT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = op8(xt, s);
+    } else {
+      float g[16];
+      if constexpr (SEEDS) {
+        // g = (dF0 head_w[:, 0] + dF1 head_w[:, 1]) / n from the pooled head
+        const float s0 = sn.x / (float)a.n, s1 = sn.y / (float)a.n;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float2 hw = hws[32 * sob + tile_idx(r, h)];
+          g[r] = s0 * hw.x + s1 * hw.y;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          g[4 * k] = gn[k].x; g[4 * k + 1] = gn[k].y; g[4 * k + 2] = gn[k].z; g[4 * k + 3] = gn[k].w;
+        }
+      }
+      bf16x8 go[2];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) db2[r] += g[r];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) go[s][k] = (__bf16)g[8 * s + k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) GF[(q * 4 + k) * 64 + lane] = make_float4(g[4 * k], g[4 * k + 1], g[4 * k + 2], g[4 * k + 3]);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(GA + srow * XS + 32 * sob + 16 * s + 8 * h) = go[s];
+      const f32x16 gt = transpose_mfma(go[0], go[1], eye);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(GT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = op8(gt, s);
+    }
+    barrier_lds();
+    fetch(tile + gridDim.x);
+
+    // ---- 2. hidden units of this wave: u, dh, du; dW1, dW2, db1; du to LDS
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      f32x16 u = {}, dh = {};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bf16x8 xa = ld8(XA + (32 * rb + lr) * XS + 16 * s + 8 * h);
+        const bf16x8 ga = ld8(GA + (32 * rb + lr) * XS + 16 * s + 8 * h);
+        u = mfma16(xa, w1b[s], u);  // (row x hidden): lane -> hidden, values -> rows
+        dh = mfma16(ga, w2b[s], dh);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float uu = u[r] + bias;
+        const float d = uu > 0.f ? dh[r] : 0.f;
+        u[r] = uu > 0.f ? uu : 0.f;  // relu(u)
+        dh[r] = d;                   // du
+        db1 += d;
+      }
+      bf16x8 duo[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int pos = 32 * rb + 16 * s + 8 * h;
+        duo[s] = op8(dh, s);
+        const bf16x8 ho = op8(u, s);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          dW1[i] = mfma16(ld8(XT + (32 * i + lr) * XS + pos), duo[s], dW1[i]);  // (in x hidden)
+          dW2[i] = mfma16(ho, ld8(GT + (32 * i + lr) * XS + pos), dW2[i]);      // (hidden x out)
+        }
+      }
+      // du transposed (lane -> row, values -> hidden units in perm16 order), 16-byte writes
+      const f32x16 dut = transpose_mfma(duo[0], duo[1], eye);
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+        *reinterpret_cast<bf16x8*>(DU + (32 * rb + lr) * DUS + 32 * w + 16 * s + 8 * h) = op8(dut, s);
+    }
+    barrier_lds();
+
+    // ---- 3. dx tile (rows of block sb, features of block sob) = g + du W1^T, hidden in halves
+    f32x16 acc = {};
+    const int k0 = gw ? 0 : (M / 16) / 2;
+#pragma unroll
+    for (int s = 0; s < (M / 16) / 2; ++s)  // A[m = in][k = hidden] = W1, B[k = hidden][n = row] = du
+      acc = mfma16(ld8(W1s + (32 * sob + lr) * DUS + 16 * (k0 + s) + 8 * h),
+                   ld8(DU + (32 * sb + lr) * DUS + 16 * (k0 + s) + 8 * h), acc);
+    if (!gw) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        XD[(q * 4 + k) * 64 + lane] = make_float4(acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]);
+    }
+    barrier_lds();
+    {
+      // stores issued by every wave (dropped unless this wave finishes a valid tile)
+      const auto ro = rsrc(a.g_out + (gb * NB + sob) * 64 * 16, (gw && gb < nblk) ? 64 * 16 * 4 : 0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float4 o = XD[(q * 4 + k) * 64 + lane], g = GF[(q * 4 + k) * 64 + lane];
+        rst4(ro, lane * 64 + 16 * k,
+             make_float4(acc[4 * k] + o.x + g.x, acc[4 * k + 1] + o.y + g.y, acc[4 * k + 2] + o.z + g.z,
+                         acc[4 * k + 3] + o.w + g.w));
+      }
+    }
+  }
+
+  // ---- write this workgroup's gradients: dW1 [D][M], dW2 [M][D], db1 [M], db2 [D]
+  float* part = a.partial + (int64_t)blockIdx.x * (2 * D * M + M + D);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      part[(32 * i + tile_idx(r, h)) * M + 32 * w + lr] = dW1[i][r];
+      part[D * M + (32 * w + tile_idx(r, h)) * D + 32 * i + lr] = dW2[i][r];
+    }
+  {
+    const float v = db1 + __shfl_xor(db1, 32, 64);
+    if (h == 0) part[2 * D * M + hid] = v;
+  }
+  // db2 (waves 4-7): the 32 rows of each lane half by a fixed butterfly, then the two blocks
+  // of the tile in a fixed order
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    float v = db2[r];
+#pragma unroll
+    for (int m = 1; m < 32; m <<= 1) v += __shfl_xor(v, m, 64);
+    if (gw && lr == 0) db2s[sb * D + 32 * sob + tile_idx(r, h)] = v;
+  }
+  __syncthreads();
+  if (t < D) part[2 * D * M + M + t] = db2s[t] + db2s[D + t];
+}
+
+size_t bwd_mlp8_bf16_lds() {
+  return (size_t)(2 * RT * XS + 2 * 64 * XS + (RT + 64) * (256 + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float) +
+         2 * 4 * 4 * 64 * sizeof(float4) + 64 * sizeof(float2);
+}
+
 size_t bwd_mlp_bf16_lds(int M) {
   return (size_t)(2 * RT * XS + 2 * 64 * XS + (RT + 64) * (M + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float) +
          4 * 4 * 64 * sizeof(float4) + 64 * sizeof(float2);
@@ -332,6 +566,16 @@ size_t bwd_mlp_bf16_lds(int M) {
 bool bwd_mlp_bf16_supported(int d, int D, int M) { return d == 64 && D == 64 && (M == 128 || M == 256); }
 
 int32_t launch_bwd_mlp_bf16(const BwdArgs& a, int blocks, hipStream_t st) {
+  const bool seeds = a.g_in == nullptr;
+  if (a.M == 256) {
+    auto go8 = [&](auto kern) -> int32_t {
+      TDO_TRY(allow_full_lds((const void*)kern));
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(512), bwd_mlp8_bf16_lds(), st, a);
+      TDO_HIP(hipGetLastError());
+      return TDO_OK;
+    };
+    return seeds ? go8(k_bwd_mlp8_bf16<true>) : go8(k_bwd_mlp8_bf16<false>);
+  }
   const size_t lds = bwd_mlp_bf16_lds(a.M);
   auto go = [&](auto kern) -> int32_t {
     TDO_TRY(allow_full_lds((const void*)kern));
@@ -339,7 +583,6 @@ int32_t launch_bwd_mlp_bf16(const BwdArgs& a, int blocks, hipStream_t st) {
     TDO_HIP(hipGetLastError());
     return TDO_OK;
   };
-  const bool seeds = a.g_in == nullptr;
   switch (a.M) {
     case 128: return seeds ? go(k_bwd_mlp_bf16<128, true>) : go(k_bwd_mlp_bf16<128, false>);
     case 256: return seeds ? go(k_bwd_mlp_bf16<256, true>) : go(k_bwd_mlp_bf16<256, false>);
