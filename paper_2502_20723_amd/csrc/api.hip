@@ -154,6 +154,7 @@ int32_t run_forward(const NetPlan& np, const NetWeights& w, const uint64_t* ecfg
     if (sv) {
       a.save_x = static_cast<char*>(sv->x) + (size_t)l * sv->layer_bytes;
       a.save_mid = static_cast<char*>(sv->mid) + (size_t)l * sv->layer_bytes;
+      a.save_lse = sv->lse ? sv->lse + (size_t)l * sv->lse_layer : nullptr;
       a.save_last = sv->last;
     }
     a.head_w = w.head_w;

@@ -2,7 +2,9 @@
 // O_h = softmax(Q_h K_h^T / sqrt(dh)) V_h, Q = x Wq, K = x Wk, V = x Wv
 // (Eq. attn-head-appendix), for width 64 with BF16 MFMA operands and FP32
 // accumulation, chains of n <= 32 sites (configurations never span blocks):
-//   dO = g W_O^T;  per head: dP = dO V^T, dS = P (dP - rowsum(P dP)) / sqrt(dh),
+//   dO = g W_O^T;  per head: P = exp2(S - lse) from the log2 row normalisers lse the forward
+//   saved (the scores S here are the same bits as there), dP = dO V^T,
+//   dS = P (dP - rowsum(P dP)) / sqrt(dh),
 //   dQ = dS K, dK = dS^T Q, dV = P^T dO;  dx = g + dQ Wq^T + dK Wk^T + dV Wv^T;
 //   dW_O += O^T g, dWq += x^T dQ, dWk += x^T dK, dWv += x^T dV.
 //
@@ -132,8 +134,14 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
   // latency of the loads is covered by the previous tile's gradient phase
   bf16x8 xn[NB][ST];
   float4 gn[NB][4];
+  float ln[HPB];  // the forward's log2 softmax normalisers of this lane's query row, heads of head block hb
   auto fetch = [&](int64_t tl) {
     const int64_t g = 4 * tl + bw;
+    {
+      const float* ls = a.lse + (((tl < ntile && g < nblk) ? g : 0) * 32 + lr) * (NB * HPB) + hb * HPB;
+#pragma unroll
+      for (int j = 0; j < HPB; ++j) ln[j] = ls[j];
+    }
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) {
       if (tl < ntile && g < nblk) {
@@ -230,6 +238,9 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
 #pragma unroll
       for (int s = 0; s < ST; ++s) { VFb[s] = op8(VF, s); OFb[s] = op8(OF, s); }
     }
+    float lse[HPB];
+#pragma unroll
+    for (int j = 0; j < HPB; ++j) lse[j] = ln[j];
     f32x16 dQR = {}, dKR = {}, dVR = {}, AOF = {};  // dQ, dK, dV (R) and the attention output O (F)
 #pragma unroll
     for (int j = 0; j < HPB; ++j) {
@@ -242,23 +253,12 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         for (int r = 0; r < 16; ++r)
           if (!((okbits >> r) & 1u)) sq[r] = -INFINITY;
       }
-      float m = -INFINITY;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) m = fmaxf(m, sq[r]);
-      m = xor32_max(m);
-      const float mm = (m == -INFINITY) ? 0.f : m;  // a query with no key keeps P = 0
-      float l = 0.f;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        sq[r] = __builtin_amdgcn_exp2f(sq[r] - mm);
-        l += sq[r];
-      }
-      l = xor32_sum(l);
-      const float il = l > 0.f ? 1.0f / l : 0.f;
+      // P from the forward's normaliser of the row (its scores are the same bits); +inf for a
+      // query with no key gives P = 0
       float dl = 0.f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        sq[r] *= il;  // P
+        sq[r] = __builtin_amdgcn_exp2f(sq[r] - lse[j]);  // P
         dl += sq[r] * dpq[r];
       }
       dl = xor32_sum(dl);
@@ -380,6 +380,7 @@ int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t s
   const size_t lds = bwd_attn_bf16_lds();
   // written for distinct input and output gradient buffers
   TDO_CHECK(a.g_in != a.g_out, TDO_EINVAL, "BF16 attention backward cannot run in place");
+  TDO_CHECK(a.lse != nullptr, TDO_EINVAL, "BF16 attention backward needs the forward's softmax normalisers");
   auto go = [&](auto kern) -> int32_t {
     TDO_TRY(allow_full_lds((const void*)kern));
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(512), lds, st, a);

@@ -258,6 +258,7 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
         for (int s = 0; s < ST; ++s) vop[kb][s] = P::op(v[kb], s);
       f32x16 o[NBR];
       float invl[NBR][HPB];
+      float lsev[HPB];  // log2 softmax normalisers of this lane's row (non-span: one row block)
 #pragma unroll
       for (int rb = 0; rb < NBR; ++rb) o[rb] = f32x16{};
 #pragma unroll
@@ -291,10 +292,19 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
             }
           l = xor32_sum(l);
           invl[qb][j] = l > 0.f ? 1.0f / l : 0.f;
+          // for the backward: P = exp2(s - lse) (+inf for a row with no key, so that P = 0)
+          if constexpr (!SPAN) lsev[j] = l > 0.f ? mm + __builtin_amdgcn_logf(l) : INFINITY;
 #pragma unroll
           for (int kb = 0; kb < NBR; ++kb)
 #pragma unroll
             for (int s = 0; s < ST; ++s) o[qb] = P::mma(mine ? vop[kb][s] : op_t{}, P::op(st[kb], s), o[qb]);
+        }
+      }
+      if constexpr (!SPAN && P::KPL == 8) {  // the head block's normalisers are contiguous per row
+        if (a.save_lse && h == 0) {
+          float* dst = a.save_lse + (gblk0 * 32 + lr) * (NB * HPB) + hb * HPB;
+#pragma unroll
+          for (int j = 0; j < HPB; ++j) dst[j] = lsev[j];
         }
       }
       // normalise per head, then W_O into the residual

@@ -17,6 +17,8 @@ struct FwdArgs {
   float* x_out;                 // residual out (not last layer)
   void* save_x;                 // optional: layer input saved for the backward pass
   void* save_mid;               // optional: input of the feed-forward sub-layer
+  float* save_lse;              // optional (BF16, n <= 32): [blocks][32 rows][D/DH heads] log2 of
+                                // each attention row's softmax normaliser (+inf for a row with no key)
   void* save_last;              // optional (last layer): output x_L
   const float* head_w;          // last layer: [d][2]
   const float* head_b;          // last layer: [2]
@@ -57,6 +59,7 @@ struct BwdArgs {
   const float* w2;
   const void* save_x;           // layer input
   const void* save_mid;         // feed-forward input
+  const float* lse;             // attention row normalisers saved by the forward (or NULL)
   const float* g_in;            // incoming gradient [blocks][D/32][64][16] (NULL: from seeds)
   const float* seeds;           // last layer: per configuration-pass (dF0, dF1), [E][2][2]
   const float* head_w;          // [d][2]

@@ -37,14 +37,17 @@ struct Saves {
   void* mid;          // [L] feed-forward inputs
   void* last;         // output of the last layer
   size_t layer_bytes; // bytes of one layer's buffer
+  float* lse;         // [L][blocks][32 rows][D/DH heads]: log2 of each attention row's softmax
+                      // normaliser (BF16 path, n <= 32; NULL otherwise)
+  size_t lse_layer;   // floats of one layer's part
 };
 
 // Workspace plan shared by the loss/gradient and VJP drivers.
 struct TrainWs {
   size_t woff[4], wback, gA, Lall, acc, lpart, mlp_acc, attn_acc, dT_acc, partial;
-  size_t cnt, off, etot, ecfg, ecoef, eowner, lr, z, dF, xa, xb, sx, smid, slast;
+  size_t cnt, off, etot, ecfg, ecoef, eowner, lr, z, dF, xa, xb, sx, smid, slast, slse;
   int64_t chunk, emax, nblk;
-  size_t layer_bytes;
+  size_t layer_bytes, lse_layer;
 };
 
 struct ModelDev;

@@ -137,6 +137,7 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
     a.b1 = w.b1 + (size_t)l * M;
     a.save_x = static_cast<const char*>(sv.x) + (size_t)l * sv.layer_bytes;
     a.save_mid = static_cast<const char*>(sv.mid) + (size_t)l * sv.layer_bytes;
+    a.lse = sv.lse ? sv.lse + (size_t)l * sv.lse_layer : nullptr;
     a.w1 = params + pp.off_layer0 + (int64_t)l * pp.layer_stride + 4LL * pp.d * pp.d;
     a.w2 = a.w1 + (int64_t)pp.d * pp.mlp + pp.mlp;
     a.head_w = w.head_w;
@@ -215,7 +216,9 @@ int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, T
   const size_t fixed = ar.used + 64 * 256;  // includes the per-sample L buffer
   const int save = np.bf16 ? 2 : 4;
   const double blocks_per_entry = np.span ? 4.0 : 2.0 / np.cpb;
-  const double per_block = 32.0 * np.D * (2 * 4 + (2 * pp.layers + 1) * save);
+  const bool keep_lse = np.bf16 && !np.span;  // consumed by the BF16 attention backward
+  const double per_block = 32.0 * np.D * (2 * 4 + (2 * pp.layers + 1) * save) +
+                           (keep_lse ? (double)pp.layers * 32 * (np.D / np.DH) * 4 : 0.0);
   const double per_entry = blocks_per_entry * per_block + 80.0;
   const double per_sample = nslots * per_entry + 32.0;
   TDO_CHECK(c.budget > fixed + per_sample + 8 * per_block, TDO_ENOMEM,
@@ -242,6 +245,8 @@ int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, T
   t->sx = ar.take<char>(t->layer_bytes * pp.layers);
   t->smid = ar.take<char>(t->layer_bytes * pp.layers);
   t->slast = ar.take<char>(t->layer_bytes);
+  t->lse_layer = keep_lse ? (size_t)t->nblk * 32 * (np.D / np.DH) : 0;
+  t->slse = ar.take<float>(t->lse_layer * pp.layers + 64);
   TDO_TRY(ensure_workspace(const_cast<Context*>(&c), ar.used));
   return TDO_OK;
 }
@@ -272,7 +277,8 @@ extern "C" int32_t tdo_log_rho_vjp(tdo_ctx_t* ctx, const tdo_arch_t* arch, const
   TDO_TRY(fill(at<double>(ws, t.dT_acc), 64LL * np.D, 0.0, stream));
   BwdBufs bb{at<char>(ws, t.wback), at<float>(ws, t.xa), at<float>(ws, t.xb), at<float>(ws, t.partial), c.num_cus,
              at<double>(ws, t.mlp_acc), at<double>(ws, t.attn_acc), at<double>(ws, t.dT_acc)};
-  Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes};
+  Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes,
+           t.lse_layer ? at<float>(ws, t.slse) : nullptr, t.lse_layer};
   for (int64_t e0 = 0; e0 < B; e0 += t.chunk) {
     const int64_t E = std::min(t.chunk, B - e0);
     const uint64_t* ec = cfg + 2 * e0;
@@ -314,7 +320,8 @@ int32_t loss_grad_run(Context& c, const NetPlan& np, const ModelDev& m, const Tr
   TDO_TRY(fill(acc, 2, 0.0, stream));
   BwdBufs bb{at<char>(ws, t.wback), at<float>(ws, t.xa), at<float>(ws, t.xb), at<float>(ws, t.partial), c.num_cus,
              at<double>(ws, t.mlp_acc), at<double>(ws, t.attn_acc), at<double>(ws, t.dT_acc)};
-  Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes};
+  Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes,
+           t.lse_layer ? at<float>(ws, t.slse) : nullptr, t.lse_layer};
   const int64_t* Ed = at<int64_t>(ws, t.etot);
   for (int64_t b0 = 0; b0 < B; b0 += t.chunk) {
     const int64_t Bc = std::min(t.chunk, B - b0);
@@ -333,8 +340,10 @@ int32_t loss_grad_run(Context& c, const NetPlan& np, const ModelDev& m, const Tr
     TDO_TRY(run_backward(np, w, bb, params, ec, t.emax, Ed, sv, at<float>(ws, t.dF), gA, stream));
   }
   if (grad_mode == 0) {  // + 2 sum_b w_b (|L_b|^2 - F) Re O(x_b), F known from the first pass
-    for (int64_t b0 = 0; b0 < B; b0 += t.chunk) {
-      const int64_t Bc = std::min(t.chunk, B - b0);
+    // one entry per sample here: the buffers sized for emax entries hold emax samples
+    const int64_t chunk2 = std::max<int64_t>(1, std::min<int64_t>(B, t.emax));
+    for (int64_t b0 = 0; b0 < B; b0 += chunk2) {
+      const int64_t Bc = std::min(chunk2, B - b0);
       const uint64_t* ec = cfg + 2 * b0;
       TDO_TRY(run_forward(np, w, ec, Bc, nullptr, at<float>(ws, t.xa), at<float>(ws, t.xb), &sv, at<float>(ws, t.z), stream));
       hipLaunchKernelGGL(k_seeds_centred, dim3(256), dim3(256), 0, stream, Bc, weights, b0, Lall + 2 * b0, acc,
