@@ -207,6 +207,9 @@ __device__ __forceinline__ float2 rld2(__amdgpu_buffer_rsrc_t r, int voff) {
 __device__ __forceinline__ float4 rld4(__amdgpu_buffer_rsrc_t r, int voff) {
   return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
 }
+__device__ __forceinline__ void rst2(__amdgpu_buffer_rsrc_t r, int voff, float2 v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(int __attribute__((ext_vector_type(2))), v), r, voff, 0, 0);
+}
 __device__ __forceinline__ void rst4(__amdgpu_buffer_rsrc_t r, int voff, float4 v) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, voff, 0, 0);
 }

@@ -118,7 +118,7 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
   const elem_t* W2 = W + 4 * D * D + D * M;
 
   const int lane = threadIdx.x & 63, h = lane >> 5, lr = lane & 31;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
   const int n = a.n, cpb = a.cpb;
   const int64_t ntiles = SPAN ? 2 * E : 2 * ((E + cpb - 1) / cpb);
@@ -300,12 +300,15 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
             for (int s = 0; s < ST; ++s) o[qb] = P::mma(mine ? vop[kb][s] : op_t{}, P::op(st[kb], s), o[qb]);
         }
       }
-      if constexpr (!SPAN && P::KPL == 8) {  // the head block's normalisers are contiguous per row
-        if (a.save_lse && h == 0) {
-          float* dst = a.save_lse + (gblk0 * 32 + lr) * (NB * HPB) + hb * HPB;
-#pragma unroll
-          for (int j = 0; j < HPB; ++j) dst[j] = lsev[j];
-        }
+      if constexpr (!SPAN && P::KPL == 8) {
+        // the head block's normalisers are contiguous per row; one store per lane of the first
+        // half (the second half's offset is out of range, and the resource is empty when nothing
+        // is saved: no branch)
+        const auto rl = rsrc(a.save_lse ? a.save_lse + gblk0 * 32 * (NB * HPB) : nullptr,
+                             a.save_lse ? 32 * NB * HPB * 4 : 0);
+        const int off = h == 0 ? (lr * (NB * HPB) + hb * HPB) * 4 : 0x7ffffff0;
+        if constexpr (HPB == 4) rst4(rl, off, make_float4(lsev[0], lsev[1], lsev[2], lsev[3]));
+        else rst2(rl, off, make_float2(lsev[0], lsev[1]));
       }
       // normalise per head, then W_O into the residual
 #pragma unroll
