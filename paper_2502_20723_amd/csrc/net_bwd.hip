@@ -492,51 +492,105 @@ __global__ void __launch_bounds__(256) k_bwd_head(const void* __restrict__ save_
   }
 }
 
-// dT[code][f] += sum over rows with that window code of dx_0[row][f], as an MFMA
-// contraction over the rows of each block: C[f][code] = sum_row dx_0[row][f] onehot[row][code]
-// (FP32 operands, exact one-hot), accumulated in registers by every wave over its
-// blocks and written to the wave's partial slot [64][D] once per launch.
+// dT[code][f] += sum over rows with that window code of dx_0[row][f], as a contraction
+// over the rows of each block: C[f][code] = sum_row dx_0[row][f] onehot[row][code].  It runs
+// on the BF16 matrix cores without losing FP32 accuracy: every FP32 value of dx_0 is split
+// exactly into three BF16 terms (hi + mid + lo = x, each term the next 8 significant bits),
+// the terms are transposed on the matrix cores (lane -> feature, values -> rows), and each is
+// multiplied by the 0/1 operand: every product is exact and the sums accumulate in FP32 as
+// in an FP32 contraction.  Accumulated in registers by every wave over its blocks and
+// written to the wave's partial slot [64][D] once per launch.
 template <int D>
 __global__ void __launch_bounds__(256) k_embed_onehot(const float* __restrict__ dx0, const uint64_t* __restrict__ ecfg,
                                                       const int64_t* E_dev, int64_t E_host, int n, int cpb, int span,
                                                       float* __restrict__ partial) {
   constexpr int NB = D / 32;
+  __shared__ uint32_t codes_s[4][8];  // per wave: window code of each of the 32 rows (byte r), 255 for padding
   const int64_t E = E_dev ? *E_dev : E_host;
   const RowMap rm{n, cpb, span != 0};
   const int64_t nblk = span ? 4 * E : 2 * ((E + cpb - 1) / cpb);
-  const int lane = threadIdx.x & 63, h = lane >> 5, lr = lane & 31, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, h = lane >> 5, lr = lane & 31;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint8_t* cb = reinterpret_cast<uint8_t*>(codes_s[wave]);
+  bf16x8 eye[2];  // permutation operands of the transposes: eye[s][t] = [tile_idx(8 s + t, h) == lr]
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int t2 = 0; t2 < 8; ++t2) eye[s2][t2] = (__bf16)(tile_idx(8 * s2 + t2, h) == lr ? 1.0f : 0.0f);
+  auto mfma16 = [](const bf16x8& a, const bf16x8& b, const f32x16& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  };
   f32x16 acc[NB][2];
 #pragma unroll
   for (int ft = 0; ft < NB; ++ft) acc[ft][0] = acc[ft][1] = f32x16{};
   for (int64_t g = (int64_t)blockIdx.x * 4 + wave; g < nblk; g += (int64_t)gridDim.x * 4) {
-    // window code of this lane's row (-1 if the row is padding)
-    int64_t e; int pass, ric; bool valid;
-    rm.at(g, lr, E, e, pass, ric, valid);
-    int code = -1;
-    if (valid) {
-      const uint64_t al = ecfg[2 * e], be = ecfg[2 * e + 1];
-      const uint64_t c0 = pass ? be : al, c1 = pass ? al : be;
-      code = 0;
-      for (int k = 0; k < 3; ++k) {
-        int s = ric + k;
-        s = s >= n ? s - n : s;
-        code += ((int)((c0 >> s) & 1ull) + 2 * (int)((c1 >> s) & 1ull)) << (2 * k);
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int row = tile_idx(s, h);
-      const int rc = __shfl(code, row, 64);  // code of the row this k-step holds
-#pragma unroll
-      for (int ft = 0; ft < NB; ++ft) {
-        // dx_0[row][32 ft + lr] from the block-major layout
-        const int fi = lr, hf = (fi >> 2) & 1, rf = 4 * (fi >> 3) + (fi & 3);
-        const float a = dx0[((g * NB + ft) * 64 + row + 32 * hf) * 16 + rf];
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          const float b = (rc == 32 * ct + lr) ? 1.0f : 0.0f;
-          acc[ft][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[ft][ct], 0, 0, 0);
+    // window code of this lane's row (255 if the row is padding), shared through LDS
+    {
+      int64_t e; int pass, ric; bool valid;
+      rm.at(g, lr, E, e, pass, ric, valid);
+      int code = 255;
+      if (valid) {
+        const uint64_t al = ecfg[2 * e], be = ecfg[2 * e + 1];
+        const uint64_t c0 = pass ? be : al, c1 = pass ? al : be;
+        code = 0;
+        for (int k = 0; k < 3; ++k) {
+          int s = ric + k;
+          s = s >= n ? s - n : s;
+          code += ((int)((c0 >> s) & 1ull) + 2 * (int)((c1 >> s) & 1ull)) << (2 * k);
         }
+      }
+      if (h == 0) cb[lr] = (uint8_t)code;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    // one-hot operands: lane (code 32 ct + lr, half h), value t of k-step s -> row tile_idx(8 s + t, h)
+    bf16x8 oh[2][2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const uint32_t w0 = codes_s[wave][4 * s + h], w1 = codes_s[wave][4 * s + 2 + h];  // rows 16s+4h.., 16s+8+4h..
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const uint32_t c = ((t < 4 ? w0 : w1) >> (8 * (t & 3))) & 255u;
+          oh[ct][s][t] = (__bf16)(c == (uint32_t)(32 * ct + lr) ? 1.0f : 0.0f);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();  // codes read before the next block's codes are written
+#pragma unroll
+    for (int ft = 0; ft < NB; ++ft) {
+      const float4* src = reinterpret_cast<const float4*>(dx0 + ((g * NB + ft) * 64 + lane) * 16);
+      float x[16];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = src[q];
+        x[4 * q] = v.x; x[4 * q + 1] = v.y; x[4 * q + 2] = v.z; x[4 * q + 3] = v.w;
+      }
+      bf16x8 tm[3][2];  // hi, mid, lo: R layout (lane -> row, values -> features tile_idx(r, h))
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const __bf16 hi = (__bf16)x[r];
+        const float r1 = x[r] - (float)hi;
+        const __bf16 mid = (__bf16)r1;
+        const __bf16 lo = (__bf16)(r1 - (float)mid);
+        tm[0][r >> 3][r & 7] = hi;
+        tm[1][r >> 3][r & 7] = mid;
+        tm[2][r >> 3][r & 7] = lo;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        // transposed term: lane -> feature 32 ft + lr, value r -> row tile_idx(r, h) (exact)
+        const f32x16 tt = mfma16(tm[k][1], eye[1], mfma16(tm[k][0], eye[0], f32x16{}));
+        bf16x8 ta[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int t = 0; t < 8; ++t) ta[s][t] = (__bf16)tt[8 * s + t];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int s = 0; s < 2; ++s) acc[ft][ct] = mfma16(ta[s], oh[ct][s], acc[ft][ct]);
       }
     }
   }
