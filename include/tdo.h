@@ -9,8 +9,9 @@
  *   word 0 = alpha, word 1 = beta (the row and column labels of
  *   rho(alpha, beta) in the vectorisation |rho>> = sum rho_ab |a>|b>, App. A).
  *   Bit i is site i; bit value 0 = spin up (sigma^z = +1), 1 = spin down.
- *   Bits at positions >= n must be zero; configurations live in device
- *   memory and are not checked (results are unspecified otherwise).
+ *   Bits at positions >= n are ignored: every result is that of the
+ *   configuration with those bits cleared (connected configurations are
+ *   written with them cleared; samples keep the bits of their inputs).
  * - Complex numbers are two consecutive floats (re, im) or doubles.
  * - Every pointer argument named as device memory must point to memory on the
  *   context's device; host pointers are marked "host".  The caller owns and

@@ -63,6 +63,8 @@ __device__ bool slot_entry(const ModelDev& m, uint64_t a, uint64_t b, int s, uin
                            uint64_t& yb, float& cre, float& cim) {
   const int n = m.n;
   const uint64_t mask = low_mask(n);
+  a &= mask;  // bits at positions >= n are ignored
+  b &= mask;
   ya = a;
   yb = b;
   if (s == 0) {
