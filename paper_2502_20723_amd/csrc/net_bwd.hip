@@ -603,68 +603,67 @@ __global__ void __launch_bounds__(256) k_embed_onehot(const float* __restrict__ 
       for (int r = 0; r < 16; ++r) part[(32 * ct + lr) * D + 32 * ft + tile_idx(r, h)] = acc[ft][ct][r];
 }
 
-// Chain rule from the table gradient dT[64][D] (FP64) into the convolution
-// parameters; one workgroup, FP64 (recomputes the table's pre-activations).
+// Chain rule from the table gradient dT[64][D] (FP64) into the convolution parameters, in FP64
+// (recomputes the table's pre-activations).  One workgroup per window code: the code's
+// contribution to every parameter gradient goes to its slot part[code][4d + d + 2d^2 + d] (the
+// gradient's layout); k_embed_params_sum adds the slots in code order.
 __global__ void __launch_bounds__(64) k_embed_params(const float* __restrict__ params, const double* __restrict__ dT,
-                                                     int d, int D, double* __restrict__ grad) {
+                                                     int d, int D, double* __restrict__ part) {
   // grad layout: conv1_w [2][2][d], conv1_b [d], conv2_w [2][d][d], conv2_b [d]
-  extern __shared__ __align__(16) char smem[];
-  double* gw2 = reinterpret_cast<double*>(smem);  // conv2_w gradient [2][d][d], accumulated over the codes
-  double* ea = gw2 + 2 * d * d;                   // [64] each
-  double *eb = ea + 64, *ga = eb + 64, *gb = ga + 64, *gpre = gb + 64;
-  float* w2s = reinterpret_cast<float*>(gpre + 64);  // conv2_w [2][d][d]
+  __shared__ double ea[64], eb[64], gpre[64];
   const float* w1 = params;
   const float* b1 = params + 4 * d;
   const float* w2 = b1 + d;
   const float* b2 = w2 + 2 * d * d;
-  double* g_w1 = grad;
-  double* g_b1 = grad + 4 * d;
-  double* g_w2 = g_b1 + d;
-  double* g_b2 = g_w2 + 2 * d * d;
+  const int64_t len = 6LL * d + 2LL * d * d;
+  double* p = part + (int64_t)blockIdx.x * len;
+  double* p_w1 = p;
+  double* p_b1 = p + 4 * d;
+  double* p_w2 = p_b1 + d;
+  double* p_b2 = p_w2 + 2 * d * d;
   auto spin = [](int t, int ch) { return 1.0 - 2.0 * (double)((t >> ch) & 1); };
   auto phi = [](double u) { return 0.5 * u * (1.0 + erf(u * 0.7071067811865476)); };
   auto dphi = [](double u) { return 0.5 * (1.0 + erf(u * 0.7071067811865476)) + u * 0.3989422804014327 * exp(-0.5 * u * u); };
-  const int t = threadIdx.x;
-  for (int i = t; i < 2 * d * d; i += 64) {
-    gw2[i] = 0.0;
-    w2s[i] = w2[i];
+  const int t = threadIdx.x, code = blockIdx.x;
+  const int t0 = code & 3, t1 = (code >> 2) & 3, t2 = (code >> 4) & 3;
+  double pa = 0, pb = 0;
+  if (t < d) {
+    pa = b1[t] + spin(t0, 0) * w1[t] + spin(t0, 1) * w1[d + t] + spin(t1, 0) * w1[2 * d + t] + spin(t1, 1) * w1[3 * d + t];
+    pb = b1[t] + spin(t1, 0) * w1[t] + spin(t1, 1) * w1[d + t] + spin(t2, 0) * w1[2 * d + t] + spin(t2, 1) * w1[3 * d + t];
+    ea[t] = phi(pa);
+    eb[t] = phi(pb);
   }
   __syncthreads();
-  for (int code = 0; code < 64; ++code) {
-    const int t0 = code & 3, t1 = (code >> 2) & 3, t2 = (code >> 4) & 3;
-    double pa = 0, pb = 0;
-    if (t < d) {
-      pa = b1[t] + spin(t0, 0) * w1[t] + spin(t0, 1) * w1[d + t] + spin(t1, 0) * w1[2 * d + t] + spin(t1, 1) * w1[3 * d + t];
-      pb = b1[t] + spin(t1, 0) * w1[t] + spin(t1, 1) * w1[d + t] + spin(t2, 0) * w1[2 * d + t] + spin(t2, 1) * w1[3 * d + t];
-      ea[t] = phi(pa);
-      eb[t] = phi(pb);
-    }
-    __syncthreads();
-    if (t < d) {  // output feature o = t: pre-activation and its gradient
-      double acc = b2[t];
-      for (int c = 0; c < d; ++c) acc += ea[c] * w2s[c * d + t] + eb[c] * w2s[d * d + c * d + t];
-      gpre[t] = dT[code * D + t] * dphi(acc);
-    }
-    __syncthreads();
-    if (t < d) {
-      g_b2[t] += gpre[t];
-      for (int o = 0; o < d; ++o) {  // thread t = input channel c
-        gw2[t * d + o] += ea[t] * gpre[o];
-        gw2[d * d + t * d + o] += eb[t] * gpre[o];
-      }
-      double da = 0, db = 0;
-      for (int o = 0; o < d; ++o) { da += w2s[t * d + o] * gpre[o]; db += w2s[d * d + t * d + o] * gpre[o]; }
-      ga[t] = da * dphi(pa);
-      gb[t] = db * dphi(pb);
-      g_b1[t] += ga[t] + gb[t];
-      g_w1[t] += spin(t0, 0) * ga[t] + spin(t1, 0) * gb[t];
-      g_w1[d + t] += spin(t0, 1) * ga[t] + spin(t1, 1) * gb[t];
-      g_w1[2 * d + t] += spin(t1, 0) * ga[t] + spin(t2, 0) * gb[t];
-      g_w1[3 * d + t] += spin(t1, 1) * ga[t] + spin(t2, 1) * gb[t];
-    }
-    __syncthreads();
+  if (t < d) {  // output feature o = t: pre-activation and its gradient
+    double acc = b2[t];
+    for (int c = 0; c < d; ++c) acc += ea[c] * w2[c * d + t] + eb[c] * w2[d * d + c * d + t];
+    gpre[t] = dT[code * D + t] * dphi(acc);
   }
-  for (int i = t; i < 2 * d * d; i += 64) g_w2[i] += gw2[i];
+  __syncthreads();
+  if (t < d) {
+    p_b2[t] = gpre[t];
+    for (int c = 0; c < d; ++c) {  // thread t = output channel o (coalesced rows)
+      p_w2[c * d + t] = ea[c] * gpre[t];
+      p_w2[d * d + c * d + t] = eb[c] * gpre[t];
+    }
+    double da = 0, db = 0;  // thread t = input channel c
+    for (int o = 0; o < d; ++o) { da += w2[t * d + o] * gpre[o]; db += w2[d * d + t * d + o] * gpre[o]; }
+    const double ga = da * dphi(pa), gb = db * dphi(pb);
+    p_b1[t] = ga + gb;
+    p_w1[t] = spin(t0, 0) * ga + spin(t1, 0) * gb;
+    p_w1[d + t] = spin(t0, 1) * ga + spin(t1, 1) * gb;
+    p_w1[2 * d + t] = spin(t1, 0) * ga + spin(t2, 0) * gb;
+    p_w1[3 * d + t] = spin(t1, 1) * ga + spin(t2, 1) * gb;
+  }
+}
+
+// grad[i] += sum over the 64 codes, in code order, of part[code][i].
+__global__ void k_embed_params_sum(const double* __restrict__ part, int64_t len, double* __restrict__ grad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < 64; ++c) s += part[c * len + i];
+    grad[i] += s;
+  }
 }
 
 // Sum nparts FP32 partials of length len in index order into FP64 out[i] (+=).
@@ -784,11 +783,13 @@ int32_t launch_embed_scatter(int D, const float* dx0, const uint64_t* ecfg, cons
   return TDO_OK;
 }
 
-int32_t launch_embed_params(const float* params, const double* dT, int d, int D, double* grad, hipStream_t st) {
+int32_t launch_embed_params(const float* params, const double* dT, int d, int D, double* grad, double* part,
+                            hipStream_t st) {
   TDO_CHECK(d <= 64, TDO_EUNSUPPORTED, "embedding chain rule: width %d > 64", d);
-  const size_t lds = (size_t)2 * d * d * (sizeof(double) + sizeof(float)) + 5 * 64 * sizeof(double);
-  TDO_TRY(allow_full_lds((const void*)k_embed_params));
-  hipLaunchKernelGGL(k_embed_params, dim3(1), dim3(64), lds, st, params, dT, d, D, grad);
+  const int64_t len = 6LL * d + 2LL * d * d;
+  hipLaunchKernelGGL(k_embed_params, dim3(64), dim3(64), 0, st, params, dT, d, D, part);
+  TDO_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_embed_params_sum, dim3((unsigned)ceil_div(len, 256)), dim3(256), 0, st, part, len, grad);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
 }

@@ -370,11 +370,318 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     for (int r = 0; r < 16; ++r) part[(32 * hb + tile_idx(r, h)) * D + 32 * j + lr] = dW[j][r];
 }
 
+// Chains of 32 < n <= 64 sites: one configuration-pass spans two blocks (rows 0-31, 32-63;
+// rows >= n are padding, and keys >= n are masked).  A workgroup of 4 waves (one per SIMD,
+// all its registers) walks tiles of 4 blocks = 2 configuration-passes; wave w handles head
+// block w % 2 of configuration-pass w / 2 over both of its blocks: score, P and dS tiles are
+// 2 x 2 (query block x key block), P comes from the forward's normalisers, dK and dV of a
+// key block sum over both query blocks.  Staging, the dx exchange through LDS and the
+// per-wave weight gradients (wave w owns all of Wq, Wk, Wv, W_O for w = 0..3) are those of
+// the kernel above with 4 waves.  Padding rows add nothing: their keys have P = 0 and
+// their incoming gradient is 0 (it is formed from the seeds of valid rows only).
+template <int DH, bool MASKED>
+__global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
+  constexpr int D = 64, NB = 2, ST = 2, HPB = 32 / DH;
+  extern __shared__ __align__(16) char smem[];
+  __bf16* Wl = reinterpret_cast<__bf16*>(smem);
+  __bf16* stg = Wl + 4 * D * D;
+  float4* xch = reinterpret_cast<float4*>(stg + 4 * NSTAGE * MAT);  // [4 blocks][NB][4][64]
+
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int cp = w >> 1, hb = w & 1;  // configuration-pass of the tile, head block
+  {
+    const int4* sf = reinterpret_cast<const int4*>(a.wf);
+    const int4* sb = reinterpret_cast<const int4*>(a.wb);
+    int4* dl = reinterpret_cast<int4*>(Wl);
+    for (int i = t; i < 3 * D * D / 8; i += 256) dl[i] = sf[i];
+    for (int i = t; i < D * D / 8; i += 256) dl[3 * D * D / 8 + i] = sb[3 * D * D / 8 + i];
+  }
+  const __bf16 *Wq = Wl, *Wk = Wl + D * D, *Wv = Wl + 2 * D * D, *WoT = Wl + 3 * D * D;
+  const __amdgpu_buffer_rsrc_t WT = rsrc(a.wb, 3 * D * D * 2);
+  __syncthreads();
+
+  const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
+  const int n = a.n;
+  const int64_t ntile = E;  // 4 blocks (2 configuration-passes) per entry
+  const float sc = a.score_scale, isd = a.inv_sqrt_dh;
+  bf16x8 eye[2];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+    for (int t2 = 0; t2 < 8; ++t2) eye[s2][t2] = (__bf16)(tile_idx(8 * s2 + t2, h) == lr ? 1.0f : 0.0f);
+  // valid keys of the second key block: rows 32 + tile_idx(r, h) < n (the first block is all valid)
+  uint32_t ok1 = 0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) ok1 |= (32 + tile_idx(r, h) < n) ? (1u << r) : 0u;
+
+  f32x16 dW[NB][NB];  // weight gradient w (Wq, Wk, Wv, W_O)
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) dW[i][j] = f32x16{};
+
+  // x, g and the forward's normalisers of the two blocks, one tile ahead
+  bf16x8 xn[2][NB][ST];
+  float4 gn[2][NB][4];
+  float ln[2][HPB];
+  auto fetch = [&](int64_t tl) {
+    const bool ok = tl < ntile;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const int64_t g = ok ? 4 * tl + 2 * cp + rb : 0;
+      const float* ls = a.lse + (g * 32 + lr) * (NB * HPB) + hb * HPB;
+#pragma unroll
+      for (int j = 0; j < HPB; ++j) ln[rb][j] = ls[j];
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_x) + ((g * NB + ib) * 64 + lane) * 16;
+        xn[rb][ib][0] = ld8(xs);
+        xn[rb][ib][1] = ld8(xs + 8);
+        const float4* gs = reinterpret_cast<const float4*>(a.g_in + ((g * NB + ib) * 64 + lane) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gn[rb][ib][q] = gs[q];
+      }
+    }
+  };
+  fetch(blockIdx.x);
+
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    // ================= block phase: head block hb of configuration-pass cp (blocks 2 cp, 2 cp + 1)
+    bf16x8 xo[2][NB][ST], go[2][NB][ST];
+    float lse[2][HPB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+      for (int j = 0; j < HPB; ++j) lse[rb][j] = ln[rb][j];
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        f32x16 gr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          gr[4 * q] = gn[rb][ib][q].x; gr[4 * q + 1] = gn[rb][ib][q].y;
+          gr[4 * q + 2] = gn[rb][ib][q].z; gr[4 * q + 3] = gn[rb][ib][q].w;
+        }
+        xo[rb][ib][0] = xn[rb][ib][0];
+        xo[rb][ib][1] = xn[rb][ib][1];
+        go[rb][ib][0] = op8(gr, 0);
+        go[rb][ib][1] = op8(gr, 1);
+      }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib) {
+        if (hb == 0) stage_ops(S + SX * MAT, 32 * ib, xo[rb][ib][0], xo[rb][ib][1], eye, lr, h);
+        else stage_ops(S + SG * MAT, 32 * ib, go[rb][ib][0], go[rb][ib][1], eye, lr, h);
+      }
+    }
+    // projections of head block hb for both blocks (see the kernel above)
+    using sop = PBF16::SOp<DH>;
+    sop QRp[2][HPB], KRp[2][HPB], VRp[2][HPB], ORp[2][HPB];
+    bf16x8 QFb[2][ST], KFb[2][ST], VFb[2][ST], OFb[2][ST];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      {
+        f32x16 QR = {}, KR = {}, QF = {}, KF = {};
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+          for (int s = 0; s < ST; ++s) {
+            const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
+            const bf16x8 wq = ld8(Wq + f * 8), wk = ld8(Wk + f * 8);
+            QR = mfma16(wq, xo[rb][ib][s], QR);
+            QF = mfma16(xo[rb][ib][s], wq, QF);
+            KR = mfma16(wk, xo[rb][ib][s], KR);
+            KF = mfma16(xo[rb][ib][s], wk, KF);
+          }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) QR[r] *= sc;
+#pragma unroll
+        for (int j = 0; j < HPB; ++j) {
+          QRp[rb][j] = PBF16::pack_head<DH>(QR, j);
+          KRp[rb][j] = PBF16::pack_head<DH>(KR, j);
+        }
+#pragma unroll
+        for (int s = 0; s < ST; ++s) { QFb[rb][s] = op8(QF, s); KFb[rb][s] = op8(KF, s); }
+      }
+      {
+        f32x16 VR = {}, OR = {}, VF = {}, OF = {};
+#pragma unroll
+        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+          for (int s = 0; s < ST; ++s) {
+            const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
+            const bf16x8 wv = ld8(Wv + f * 8), wo = ld8(WoT + f * 8);
+            VR = mfma16(wv, xo[rb][ib][s], VR);
+            VF = mfma16(xo[rb][ib][s], wv, VF);
+            OR = mfma16(wo, go[rb][ib][s], OR);
+            OF = mfma16(go[rb][ib][s], wo, OF);
+          }
+#pragma unroll
+        for (int j = 0; j < HPB; ++j) {
+          VRp[rb][j] = PBF16::pack_head<DH>(VR, j);
+          ORp[rb][j] = PBF16::pack_head<DH>(OR, j);
+        }
+#pragma unroll
+        for (int s = 0; s < ST; ++s) { VFb[rb][s] = op8(VF, s); OFb[rb][s] = op8(OF, s); }
+      }
+    }
+    f32x16 dQR[2], dKR[2], dVR[2], AOF[2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) dQR[rb] = dKR[rb] = dVR[rb] = AOF[rb] = f32x16{};
+#pragma unroll
+    for (int j = 0; j < HPB; ++j) {
+      const bool mine = (lr / DH) == j;
+      const bf16x8 z = {};
+#pragma unroll
+      for (int qb = 0; qb < 2; ++qb) {
+        // query-major tiles of query block qb against key block kb
+        f32x16 sq[2], dpq[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+          sq[kb] = PBF16::scores_packed<DH>(KRp[kb][j], QRp[qb][j], f32x16{});
+          dpq[kb] = PBF16::scores_packed<DH>(VRp[kb][j], ORp[qb][j], f32x16{});
+        }
+        if constexpr (MASKED) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            if (!((ok1 >> r) & 1u)) sq[1][r] = -INFINITY;
+        }
+        float dl = 0.f;
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            sq[kb][r] = __builtin_amdgcn_exp2f(sq[kb][r] - lse[qb][j]);  // P
+            dl += sq[kb][r] * dpq[kb][r];
+          }
+        dl = xor32_sum(dl);
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) dpq[kb][r] = sq[kb][r] * (dpq[kb][r] - dl) * isd;  // dS
+          bf16x8 Pq[ST], Sq[ST];
+#pragma unroll
+          for (int s = 0; s < ST; ++s) { Pq[s] = op8(sq[kb], s); Sq[s] = op8(dpq[kb], s); }
+          const f32x16 pk = transpose_mfma(Pq[0], Pq[1], eye), sk2 = transpose_mfma(Sq[0], Sq[1], eye);
+#pragma unroll
+          for (int s = 0; s < ST; ++s) {
+            const bf16x8 Pk = op8(pk, s), Sk = op8(sk2, s);
+            AOF[qb] = mfma16(Pq[s], mine ? VFb[kb][s] : z, AOF[qb]);  // O[q][f]  += P[q][k] V[k][f]
+            dQR[qb] = mfma16(mine ? KFb[kb][s] : z, Sq[s], dQR[qb]);  // dQ[q][f] += dS[q][k] K[k][f]
+            dKR[kb] = mfma16(mine ? QFb[qb][s] : z, Sk, dKR[kb]);     // dK[k][f] += dS[q][k] Q[q][f]
+            dVR[kb] = mfma16(mine ? OFb[qb][s] : z, Pk, dVR[kb]);     // dV[k][f] += P[q][k] dO[q][f]
+          }
+        }
+      }
+    }
+    bf16x8 dq[2][ST], dk[2][ST], dv[2][ST];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
+#pragma unroll
+      for (int s = 0; s < ST; ++s) { dq[rb][s] = op8(dQR[rb], s); dk[rb][s] = op8(dKR[rb], s); dv[rb][s] = op8(dVR[rb], s); }
+      stage_ops(S + SQ * MAT, 32 * hb, dq[rb][0], dq[rb][1], eye, lr, h);
+      stage_ops(S + SK * MAT, 32 * hb, dk[rb][0], dk[rb][1], eye, lr, h);
+      stage_ops(S + SV * MAT, 32 * hb, dv[rb][0], dv[rb][1], eye, lr, h);
+#pragma unroll
+      for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + soff(32 * hb + lr, 2 * s + h)) = op8(AOF[rb], s);
+    }
+    // dx (as in the kernel above): head block 0 leaves g + its terms in LDS, head block 1 adds
+    auto dx_terms = [&](int rb, int ob) {
+      f32x16 acc = {};
+      const int voff = (hb * ST * 64 + lane) * 16;
+#pragma unroll
+      for (int s = 0; s < ST; ++s) {
+        const int so = (ob * NB * ST + s) * 64 * 16;
+        acc = mfma16(rld8(WT, voff, so), dq[rb][s], acc);
+        acc = mfma16(rld8(WT, voff, so + D * D * 2), dk[rb][s], acc);
+        acc = mfma16(rld8(WT, voff, so + 2 * D * D * 2), dv[rb][s], acc);
+      }
+      return acc;
+    };
+    if (hb == 0) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int64_t gb = 4 * tile + 2 * cp + rb;
+        float4* X = xch + (2 * cp + rb) * NB * 4 * 64;
+        float4 sv[NB][4];
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sv[ob][q] = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + ob) * 64 + lane) * 16)[q];
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) {
+          const f32x16 acc = dx_terms(rb, ob);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            X[(ob * 4 + q) * 64 + lane] = make_float4(sv[ob][q].x + acc[4 * q], sv[ob][q].y + acc[4 * q + 1],
+                                                       sv[ob][q].z + acc[4 * q + 2], sv[ob][q].w + acc[4 * q + 3]);
+        }
+      }
+    }
+    barrier_lds();  // staging and head block 0's part of dx in LDS
+    if (hb == 1) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int64_t gb = 4 * tile + 2 * cp + rb;
+        const float4* X = xch + (2 * cp + rb) * NB * 4 * 64;
+#pragma unroll
+        for (int ob = 0; ob < NB; ++ob) {
+          const f32x16 acc = dx_terms(rb, ob);
+          float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + ob) * 64 + lane) * 16);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 v = X[(ob * 4 + q) * 64 + lane];
+            dst[q] = make_float4(v.x + acc[4 * q], v.y + acc[4 * q + 1], v.z + acc[4 * q + 2], v.w + acc[4 * q + 3]);
+          }
+        }
+      }
+    }
+    fetch(tile + gridDim.x);
+
+    // ================= gradient phase: wave w adds the tile's rows into weight gradient w
+    {
+      const int am = (w < 3) ? SX : SO;
+      const int bm = (w < 3) ? SQ + w : SG;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const __bf16* A = stg + (b * NSTAGE + am) * MAT;
+        const __bf16* B = stg + (b * NSTAGE + bm) * MAT;
+#pragma unroll
+        for (int s = 0; s < ST; ++s) {
+          bf16x8 av[NB], bv[NB];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            av[i] = ld8(A + soff(32 * i + lr, 2 * s + h));
+            bv[i] = ld8(B + soff(32 * i + lr, 2 * s + h));
+          }
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) dW[i][j] = mfma16(av[i], bv[j], dW[i][j]);
+        }
+      }
+    }
+    barrier_lds();  // staging read before the next tile overwrites it
+  }
+
+  float* part = a.partial + (int64_t)blockIdx.x * 4 * D * D + (int64_t)w * D * D;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) part[(32 * i + tile_idx(r, h)) * D + 32 * j + lr] = dW[i][j][r];
+}
+
 size_t bwd_attn_bf16_lds() {
   return (size_t)(4 * 64 * 64 + 4 * NSTAGE * MAT) * sizeof(__bf16) + 4 * 2 * 64 * 16 * sizeof(float);
 }
 
-bool bwd_attn_bf16_supported(int d, int D, int DH, bool span) { return d == 64 && D == 64 && !span && (DH == 8 || DH == 16); }
+bool bwd_attn_bf16_supported(int d, int D, int DH, bool span) { return d == 64 && D == 64 && (DH == 8 || DH == 16); }
 
 int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t st) {
   const size_t lds = bwd_attn_bf16_lds();
@@ -387,6 +694,18 @@ int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t s
     TDO_HIP(hipGetLastError());
     return TDO_OK;
   };
+  if (a.span) {
+    auto go4 = [&](auto kern) -> int32_t {
+      TDO_TRY(allow_full_lds((const void*)kern));
+      hipLaunchKernelGGL(kern, dim3(blocks), dim3(256), lds, st, a);
+      TDO_HIP(hipGetLastError());
+      return TDO_OK;
+    };
+    const bool m = a.n < 64;
+    if (DH == 8) return m ? go4(k_bwd_attn_span_bf16<8, true>) : go4(k_bwd_attn_span_bf16<8, false>);
+    if (DH == 16) return m ? go4(k_bwd_attn_span_bf16<16, true>) : go4(k_bwd_attn_span_bf16<16, false>);
+    return set_error(TDO_EUNSUPPORTED, "BF16 attention backward: head width %d", DH);
+  }
   if (DH == 8) return a.masked ? go(k_bwd_attn_bf16<8, true>) : go(k_bwd_attn_bf16<8, false>);
   if (DH == 16) return a.masked ? go(k_bwd_attn_bf16<16, true>) : go(k_bwd_attn_bf16<16, false>);
   return set_error(TDO_EUNSUPPORTED, "BF16 attention backward: head width %d", DH);

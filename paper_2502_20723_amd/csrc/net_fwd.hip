@@ -258,7 +258,7 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
         for (int s = 0; s < ST; ++s) vop[kb][s] = P::op(v[kb], s);
       f32x16 o[NBR];
       float invl[NBR][HPB];
-      float lsev[HPB];  // log2 softmax normalisers of this lane's row (non-span: one row block)
+      float lsev[NBR][HPB];  // log2 softmax normalisers of this lane's row in each row block
 #pragma unroll
       for (int rb = 0; rb < NBR; ++rb) o[rb] = f32x16{};
 #pragma unroll
@@ -293,22 +293,25 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
           l = xor32_sum(l);
           invl[qb][j] = l > 0.f ? 1.0f / l : 0.f;
           // for the backward: P = exp2(s - lse) (+inf for a row with no key, so that P = 0)
-          if constexpr (!SPAN) lsev[j] = l > 0.f ? mm + __builtin_amdgcn_logf(l) : INFINITY;
+          lsev[qb][j] = l > 0.f ? mm + __builtin_amdgcn_logf(l) : INFINITY;
 #pragma unroll
           for (int kb = 0; kb < NBR; ++kb)
 #pragma unroll
             for (int s = 0; s < ST; ++s) o[qb] = P::mma(mine ? vop[kb][s] : op_t{}, P::op(st[kb], s), o[qb]);
         }
       }
-      if constexpr (!SPAN && P::KPL == 8) {
+      if constexpr (P::KPL == 8) {
         // the head block's normalisers are contiguous per row; one store per lane of the first
         // half (the second half's offset is out of range, and the resource is empty when nothing
         // is saved: no branch)
         const auto rl = rsrc(a.save_lse ? a.save_lse + gblk0 * 32 * (NB * HPB) : nullptr,
-                             a.save_lse ? 32 * NB * HPB * 4 : 0);
-        const int off = h == 0 ? (lr * (NB * HPB) + hb * HPB) * 4 : 0x7ffffff0;
-        if constexpr (HPB == 4) rst4(rl, off, make_float4(lsev[0], lsev[1], lsev[2], lsev[3]));
-        else rst2(rl, off, make_float2(lsev[0], lsev[1]));
+                             a.save_lse ? NBR * 32 * NB * HPB * 4 : 0);
+#pragma unroll
+        for (int qb = 0; qb < NBR; ++qb) {
+          const int off = h == 0 ? ((qb * 32 + lr) * (NB * HPB) + hb * HPB) * 4 : 0x7ffffff0;
+          if constexpr (HPB == 4) rst4(rl, off, make_float4(lsev[qb][0], lsev[qb][1], lsev[qb][2], lsev[qb][3]));
+          else rst2(rl, off, make_float2(lsev[qb][0], lsev[qb][1]));
+        }
       }
       // normalise per head, then W_O into the residual
 #pragma unroll

@@ -17,7 +17,7 @@ struct FwdArgs {
   float* x_out;                 // residual out (not last layer)
   void* save_x;                 // optional: layer input saved for the backward pass
   void* save_mid;               // optional: input of the feed-forward sub-layer
-  float* save_lse;              // optional (BF16, n <= 32): [blocks][32 rows][D/DH heads] log2 of
+  float* save_lse;              // optional (BF16): [blocks][32 rows][D/DH heads] log2 of
                                 // each attention row's softmax normaliser (+inf for a row with no key)
   void* save_last;              // optional (last layer): output x_L
   const float* head_w;          // last layer: [d][2]
@@ -84,7 +84,9 @@ int32_t launch_bwd_head(bool bf16, int D, const void* save_last, const float* se
                         int64_t E_host, int n, int cpb, int span, int d_real, double* gw, double* gb, hipStream_t st);
 int32_t launch_embed_scatter(int D, const float* dx0, const uint64_t* ecfg, const int64_t* E_dev, int64_t E_host,
                              int n, int cpb, int span, float* partial, int blocks, hipStream_t st);
-int32_t launch_embed_params(const float* params, const double* dT, int d, int D, double* grad, hipStream_t st);
+// part: FP64 scratch of 64 * (6 d + 2 d^2) values (one slot per window code).
+int32_t launch_embed_params(const float* params, const double* dT, int d, int D, double* grad, double* part,
+                            hipStream_t st);
 int32_t launch_reduce_partials(const float* part, int nparts, int64_t len, double* out, hipStream_t st);
 int32_t launch_scatter_layer(const double* mlp, const double* attn, int d, int D, int M, double scale, double* g,
                              hipStream_t st);

@@ -38,7 +38,7 @@ struct Saves {
   void* last;         // output of the last layer
   size_t layer_bytes; // bytes of one layer's buffer
   float* lse;         // [L][blocks][32 rows][D/DH heads]: log2 of each attention row's softmax
-                      // normaliser (BF16 path, n <= 32; NULL otherwise)
+                      // normaliser (BF16 path; NULL otherwise)
   size_t lse_layer;   // floats of one layer's part
 };
 

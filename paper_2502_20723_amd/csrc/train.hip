@@ -191,7 +191,8 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
 }
 
 static int32_t finish_backward(const NetPlan& np, const BwdBufs& bb, const float* params, double* gt, hipStream_t st) {
-  return launch_embed_params(params, bb.dT_acc, np.pp.d, np.D, gt, st);
+  // the per-code slots reuse the partial buffer, idle at this point (sized for them in plan_train)
+  return launch_embed_params(params, bb.dT_acc, np.pp.d, np.D, gt, reinterpret_cast<double*>(bb.partial), st);
 }
 
 
@@ -210,13 +211,15 @@ int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, T
   t->mlp_acc = ar.take<double>(mlen);
   t->attn_acc = ar.take<double>(4LL * np.D * np.D);
   t->dT_acc = ar.take<double>(64LL * np.D);
-  // per CU: the feed-forward or attention weight partials, or 8 wave partials of the table gradient
-  const int64_t maxlen = std::max<int64_t>(std::max<int64_t>(mlen, 4LL * np.D * np.D), 8 * 64LL * np.D);
+  // per CU: the feed-forward or attention weight partials, or 8 wave partials of the table gradient;
+  // in all, at least the FP64 per-code slots of the embedding chain rule
+  const int64_t maxlen = std::max<int64_t>(std::max<int64_t>(std::max<int64_t>(mlen, 4LL * np.D * np.D), 8 * 64LL * np.D),
+                                           (2 * 64 * (6LL * pp.d + 2LL * pp.d * pp.d) + c.num_cus - 1) / c.num_cus);
   t->partial = ar.take<float>((size_t)c.num_cus * maxlen);
   const size_t fixed = ar.used + 64 * 256;  // includes the per-sample L buffer
   const int save = np.bf16 ? 2 : 4;
   const double blocks_per_entry = np.span ? 4.0 : 2.0 / np.cpb;
-  const bool keep_lse = np.bf16 && !np.span;  // consumed by the BF16 attention backward
+  const bool keep_lse = np.bf16;  // consumed by the BF16 attention backward
   const double per_block = 32.0 * np.D * (2 * 4 + (2 * pp.layers + 1) * save) +
                            (keep_lse ? (double)pp.layers * 32 * (np.D / np.DH) * 4 : 0.0);
   const double per_entry = blocks_per_entry * per_block + 80.0;
