@@ -29,9 +29,24 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // Feature (or row) index held by value r of lane half h in a 32x32 result tile.
 __host__ __device__ constexpr int tile_idx(int r, int h) { return 8 * (r >> 2) + 4 * h + (r & 3); }
 
-__device__ __forceinline__ short bf16_bits(float x) {
-  __bf16 b = (__bf16)x;
-  return __builtin_bit_cast(short, b);
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Two FP32 values rounded to BF16 (round to nearest even) in one register, a in the low half.
+// Written as one two-element conversion so that it is one v_cvt_pk_bf16_f32; element-wise
+// conversions are sometimes emitted as one conversion per value plus a v_perm_b32.
+__device__ __forceinline__ uint32_t pk2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+// BF16 operand of values 8s .. 8s+7 of a result tile (f32x16 or float[16]).
+template <class V>
+__device__ __forceinline__ bf16x8 cvt8(const V& v, int s) {
+  u32x4 w;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = pk2(v[8 * s + 2 * i], v[8 * s + 2 * i + 1]);
+  return __builtin_bit_cast(bf16x8, w);
 }
 
 // ------------------------------------------------------------------ precisions
@@ -45,12 +60,7 @@ struct PBF16 {
   __device__ static __forceinline__ f32x16 mma(op_t a, op_t b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
-  __device__ static __forceinline__ op_t op(const f32x16& v, int s) {
-    op_t o;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) o[t] = (__bf16)v[8 * s + t];
-    return o;
-  }
+  __device__ static __forceinline__ op_t op(const f32x16& v, int s) { return cvt8(v, s); }
   // Score operand of one head: its DH features of a 32-feature result tile
   // (values [DH/2*j, DH/2*j + DH/2) of each lane), packed once and reused.
   template <int DH>
@@ -60,13 +70,8 @@ struct PBF16 {
   template <int DH>
   __device__ static __forceinline__ SOp<DH> pack_head(const f32x16& x, int j) {
     SOp<DH> o;
-    if constexpr (DH == 8) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) o.v[t] = bf16_bits(x[4 * j + t]);
-    } else {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) o.v[t] = (__bf16)x[8 * j + t];
-    }
+    if constexpr (DH == 8) o.v = __builtin_bit_cast(s16x4, (u32x2){pk2(x[4 * j], x[4 * j + 1]), pk2(x[4 * j + 2], x[4 * j + 3])});
+    else o.v = cvt8(x, j);
     return o;
   }
   template <int DH>
@@ -77,18 +82,8 @@ struct PBF16 {
   // Attention scores over DH features of head j (values [DH/2*j, DH/2*j + DH/2)).
   template <int DH>
   __device__ static __forceinline__ f32x16 scores(const f32x16& kv, const f32x16& qv, int j, f32x16 c) {
-    if constexpr (DH == 8) {
-      s16x4 a, b;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) { a[t] = bf16_bits(kv[4 * j + t]); b[t] = bf16_bits(qv[4 * j + t]); }
-      return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
-    } else {
-      static_assert(DH == 16, "head width 8 or 16");
-      bf16x8 a, b;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) { a[t] = (__bf16)kv[8 * j + t]; b[t] = (__bf16)qv[8 * j + t]; }
-      return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-    }
+    static_assert(DH == 8 || DH == 16, "head width 8 or 16");
+    return scores_packed<DH>(pack_head<DH>(kv, j), pack_head<DH>(qv, j), c);
   }
 };
 

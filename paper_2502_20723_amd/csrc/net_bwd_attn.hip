@@ -54,12 +54,6 @@ __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cas
 __device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ bf16x8 op8(const f32x16& v, int s) {
-  bf16x8 o;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) o[t] = (__bf16)v[8 * s + t];
-  return o;
-}
 // Exact transpose of a 32x32 tile on the matrix cores.  With the tile as A operand
 // (lane -> m, values -> k in the result order of the k-steps) and the 0/1 matrix
 // B[k][n] = [index of k == n] (eye, built once), C = A B has lanes enumerating the
@@ -75,7 +69,7 @@ __device__ __forceinline__ void stage_ops(__bf16* m, int f0, const bf16x8& o0, c
                                           const bf16x8 (&eye)[2], int lr, int h) {
   const f32x16 t = transpose_mfma(o0, o1, eye);  // lane -> feature f0 + lr, values -> rows
 #pragma unroll
-  for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(m + soff(f0 + lr, 2 * s + h)) = op8(t, s);
+  for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(m + soff(f0 + lr, 2 * s + h)) = cvt8(t, s);
 }
 
 }  // namespace
@@ -176,8 +170,8 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       }
       xo[ib][0] = xn[ib][0];
       xo[ib][1] = xn[ib][1];
-      go[ib][0] = op8(gr, 0);
-      go[ib][1] = op8(gr, 1);
+      go[ib][0] = cvt8(gr, 0);
+      go[ib][1] = cvt8(gr, 1);
     }
     // the wave of head block 0 stages x, the other g
 #pragma unroll
@@ -215,7 +209,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         KRp[j] = PBF16::pack_head<DH>(KR, j);
       }
 #pragma unroll
-      for (int s = 0; s < ST; ++s) { QFb[s] = op8(QF, s); KFb[s] = op8(KF, s); }
+      for (int s = 0; s < ST; ++s) { QFb[s] = cvt8(QF, s); KFb[s] = cvt8(KF, s); }
     }
     {
       f32x16 VR = {}, OR = {}, VF = {}, OF = {};  // V and dO = g W_O^T
@@ -236,7 +230,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         ORp[j] = PBF16::pack_head<DH>(OR, j);
       }
 #pragma unroll
-      for (int s = 0; s < ST; ++s) { VFb[s] = op8(VF, s); OFb[s] = op8(OF, s); }
+      for (int s = 0; s < ST; ++s) { VFb[s] = cvt8(VF, s); OFb[s] = cvt8(OF, s); }
     }
     float lse[HPB];
 #pragma unroll
@@ -266,14 +260,14 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       for (int r = 0; r < 16; ++r) dpq[r] = sq[r] * (dpq[r] - dl) * isd;  // dS
       bf16x8 Pq[ST], Sq[ST];
 #pragma unroll
-      for (int s = 0; s < ST; ++s) { Pq[s] = op8(sq, s); Sq[s] = op8(dpq, s); }
+      for (int s = 0; s < ST; ++s) { Pq[s] = cvt8(sq, s); Sq[s] = cvt8(dpq, s); }
       // key-major P and dS (lane -> key, values -> queries): exact MFMA transposes
       const f32x16 pk = transpose_mfma(Pq[0], Pq[1], eye), sk2 = transpose_mfma(Sq[0], Sq[1], eye);
       bf16x8 Pk[ST], Sk[ST];
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
-        Pk[s] = op8(pk, s);
-        Sk[s] = op8(sk2, s);
+        Pk[s] = cvt8(pk, s);
+        Sk[s] = cvt8(sk2, s);
       }
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
@@ -287,12 +281,12 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     // stage dQ, dK, dV (R layout -> [feature][row]) and O (F layout: two 16-byte writes per lane)
     bf16x8 dq[ST], dk[ST], dv[ST];
 #pragma unroll
-    for (int s = 0; s < ST; ++s) { dq[s] = op8(dQR, s); dk[s] = op8(dKR, s); dv[s] = op8(dVR, s); }
+    for (int s = 0; s < ST; ++s) { dq[s] = cvt8(dQR, s); dk[s] = cvt8(dKR, s); dv[s] = cvt8(dVR, s); }
     stage_ops(S + SQ * MAT, 32 * hb, dq[0], dq[1], eye, lr, h);
     stage_ops(S + SK * MAT, 32 * hb, dk[0], dk[1], eye, lr, h);
     stage_ops(S + SV * MAT, 32 * hb, dv[0], dv[1], eye, lr, h);
 #pragma unroll
-    for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + soff(32 * hb + lr, 2 * s + h)) = op8(AOF, s);
+    for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + soff(32 * hb + lr, 2 * s + h)) = cvt8(AOF, s);
     // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T.  The wave of head block 0 adds its terms to g and
     // leaves the sum in LDS; after the barrier the wave of head block 1 adds its terms and
     // writes dx (lane l of both waves holds the same rows and features).  The products start
@@ -464,8 +458,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
         }
         xo[rb][ib][0] = xn[rb][ib][0];
         xo[rb][ib][1] = xn[rb][ib][1];
-        go[rb][ib][0] = op8(gr, 0);
-        go[rb][ib][1] = op8(gr, 1);
+        go[rb][ib][0] = cvt8(gr, 0);
+        go[rb][ib][1] = cvt8(gr, 1);
       }
     }
 #pragma unroll
@@ -504,7 +498,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           KRp[rb][j] = PBF16::pack_head<DH>(KR, j);
         }
 #pragma unroll
-        for (int s = 0; s < ST; ++s) { QFb[rb][s] = op8(QF, s); KFb[rb][s] = op8(KF, s); }
+        for (int s = 0; s < ST; ++s) { QFb[rb][s] = cvt8(QF, s); KFb[rb][s] = cvt8(KF, s); }
       }
       {
         f32x16 VR = {}, OR = {}, VF = {}, OF = {};
@@ -525,7 +519,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           ORp[rb][j] = PBF16::pack_head<DH>(OR, j);
         }
 #pragma unroll
-        for (int s = 0; s < ST; ++s) { VFb[rb][s] = op8(VF, s); OFb[rb][s] = op8(OF, s); }
+        for (int s = 0; s < ST; ++s) { VFb[rb][s] = cvt8(VF, s); OFb[rb][s] = cvt8(OF, s); }
       }
     }
     f32x16 dQR[2], dKR[2], dVR[2], AOF[2];
@@ -564,11 +558,11 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           for (int r = 0; r < 16; ++r) dpq[kb][r] = sq[kb][r] * (dpq[kb][r] - dl) * isd;  // dS
           bf16x8 Pq[ST], Sq[ST];
 #pragma unroll
-          for (int s = 0; s < ST; ++s) { Pq[s] = op8(sq[kb], s); Sq[s] = op8(dpq[kb], s); }
+          for (int s = 0; s < ST; ++s) { Pq[s] = cvt8(sq[kb], s); Sq[s] = cvt8(dpq[kb], s); }
           const f32x16 pk = transpose_mfma(Pq[0], Pq[1], eye), sk2 = transpose_mfma(Sq[0], Sq[1], eye);
 #pragma unroll
           for (int s = 0; s < ST; ++s) {
-            const bf16x8 Pk = op8(pk, s), Sk = op8(sk2, s);
+            const bf16x8 Pk = cvt8(pk, s), Sk = cvt8(sk2, s);
             AOF[qb] = mfma16(Pq[s], mine ? VFb[kb][s] : z, AOF[qb]);  // O[q][f]  += P[q][k] V[k][f]
             dQR[qb] = mfma16(mine ? KFb[kb][s] : z, Sq[s], dQR[qb]);  // dQ[q][f] += dS[q][k] K[k][f]
             dKR[kb] = mfma16(mine ? QFb[qb][s] : z, Sk, dKR[kb]);     // dK[k][f] += dS[q][k] Q[q][f]
@@ -582,12 +576,12 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
     for (int rb = 0; rb < 2; ++rb) {
       __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
 #pragma unroll
-      for (int s = 0; s < ST; ++s) { dq[rb][s] = op8(dQR[rb], s); dk[rb][s] = op8(dKR[rb], s); dv[rb][s] = op8(dVR[rb], s); }
+      for (int s = 0; s < ST; ++s) { dq[rb][s] = cvt8(dQR[rb], s); dk[rb][s] = cvt8(dKR[rb], s); dv[rb][s] = cvt8(dVR[rb], s); }
       stage_ops(S + SQ * MAT, 32 * hb, dq[rb][0], dq[rb][1], eye, lr, h);
       stage_ops(S + SK * MAT, 32 * hb, dk[rb][0], dk[rb][1], eye, lr, h);
       stage_ops(S + SV * MAT, 32 * hb, dv[rb][0], dv[rb][1], eye, lr, h);
 #pragma unroll
-      for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + soff(32 * hb + lr, 2 * s + h)) = op8(AOF[rb], s);
+      for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + soff(32 * hb + lr, 2 * s + h)) = cvt8(AOF[rb], s);
     }
     // dx (as in the kernel above): head block 0 leaves g + its terms in LDS, head block 1 adds
     auto dx_terms = [&](int rb, int ob) {

@@ -49,12 +49,6 @@ __device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ bf16x8 op8(const f32x16& v, int s) {
-  bf16x8 o;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) o[t] = (__bf16)v[8 * s + t];
-  return o;
-}
 
 // Exact transpose of a 32x32 tile on the matrix cores, given as the two BF16
 // operands of its R layout (lane -> m, values -> tile_idx(8 s + t, h)): the
@@ -192,9 +186,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) db2[r] += g[r];
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int k = 0; k < 8; ++k) go[s][k] = (__bf16)g[8 * s + k];
+        for (int s = 0; s < 2; ++s) go[s] = cvt8(g, s);
         // the same wave and lane form the dx tile (block sb, features sob) in phase 3
 #pragma unroll
         for (int q = 0; q < 4; ++q) GF[(w * 4 + q) * 64 + lane] = make_float4(g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]);
@@ -211,8 +203,8 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
       const f32x16 xt = transpose_mfma(xo[0], xo[1], eye), gt = transpose_mfma(go[0], go[1], eye);
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        *reinterpret_cast<bf16x8*>(XT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = op8(xt, s);
-        *reinterpret_cast<bf16x8*>(GT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = op8(gt, s);
+        *reinterpret_cast<bf16x8*>(XT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = cvt8(xt, s);
+        *reinterpret_cast<bf16x8*>(GT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = cvt8(gt, s);
       }
     }
     barrier_lds();
@@ -256,8 +248,8 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
         }
 #pragma unroll
         for (int nt = 0; nt < HT; ++nt) {
-          duo[nt][s] = op8(dh[nt], s);
-          const bf16x8 ho = op8(u[nt], s);
+          duo[nt][s] = cvt8(dh[nt], s);
+          const bf16x8 ho = cvt8(u[nt], s);
 #pragma unroll
           for (int i = 0; i < NB; ++i) {
             dW1[i][nt] = mfma16(xt[i], duo[nt][s], dW1[i][nt]);  // (in x hidden)
@@ -271,7 +263,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
         const f32x16 dut = transpose_mfma(duo[nt][0], duo[nt][1], eye);
 #pragma unroll
         for (int s = 0; s < 2; ++s)
-          *reinterpret_cast<bf16x8*>(DU + (32 * rb + lr) * DUS + hid0 + 32 * nt + 16 * s + 8 * h) = op8(dut, s);
+          *reinterpret_cast<bf16x8*>(DU + (32 * rb + lr) * DUS + hid0 + 32 * nt + 16 * s + 8 * h) = cvt8(dut, s);
       }
     }
     barrier_lds();
@@ -427,7 +419,7 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
       for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(XA + srow * XS + 32 * sob + 16 * s + 8 * h) = xn[s];
       const f32x16 xt = transpose_mfma(xn[0], xn[1], eye);
 #pragma unroll
-      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(XT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = op8(xt, s);
+      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(XT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = cvt8(xt, s);
     } else {
       float g[16];
       if constexpr (SEEDS) {
@@ -448,16 +440,14 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) db2[r] += g[r];
 #pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) go[s][k] = (__bf16)g[8 * s + k];
+      for (int s = 0; s < 2; ++s) go[s] = cvt8(g, s);
 #pragma unroll
       for (int k = 0; k < 4; ++k) GF[(q * 4 + k) * 64 + lane] = make_float4(g[4 * k], g[4 * k + 1], g[4 * k + 2], g[4 * k + 3]);
 #pragma unroll
       for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(GA + srow * XS + 32 * sob + 16 * s + 8 * h) = go[s];
       const f32x16 gt = transpose_mfma(go[0], go[1], eye);
 #pragma unroll
-      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(GT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = op8(gt, s);
+      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(GT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = cvt8(gt, s);
     }
     barrier_lds();
     fetch(tile + gridDim.x);
@@ -485,8 +475,8 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int pos = 32 * rb + 16 * s + 8 * h;
-        duo[s] = op8(dh, s);
-        const bf16x8 ho = op8(u, s);
+        duo[s] = cvt8(dh, s);
+        const bf16x8 ho = cvt8(u, s);
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
           dW1[i] = mfma16(ld8(XT + (32 * i + lr) * XS + pos), duo[s], dW1[i]);  // (in x hidden)
@@ -497,7 +487,7 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
       const f32x16 dut = transpose_mfma(duo[0], duo[1], eye);
 #pragma unroll
       for (int s = 0; s < 2; ++s)
-        *reinterpret_cast<bf16x8*>(DU + (32 * rb + lr) * DUS + 32 * w + 16 * s + 8 * h) = op8(dut, s);
+        *reinterpret_cast<bf16x8*>(DU + (32 * rb + lr) * DUS + 32 * w + 16 * s + 8 * h) = cvt8(dut, s);
     }
     barrier_lds();
 

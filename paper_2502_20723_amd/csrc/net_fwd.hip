@@ -75,7 +75,11 @@ __global__ void k_embed_table(const float* __restrict__ params, int d, int D, fl
 template <class P, bool SPAN>
 constexpr int fwd_threads() { return (P::KPL == 8 && !SPAN) ? 512 : 256; }
 
-template <class P, int D, int DH, bool SPAN>
+// MBC: the feed-forward width in 32-column chunks when fixed at compile time (0: a.M / 32), so
+// that the chunk loop unrolls and one chunk's LDS reads overlap the previous chunk's products.
+// MASKED: some (query, key) pairs of a tile are invalid (several configurations per block, or
+// padding rows); a compile-time choice, so that the unmasked kernel holds no mask registers.
+template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED>
 __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs a) {
   constexpr int NB = D / 32;            // feature blocks
   constexpr int NBR = SPAN ? 2 : 1;     // row blocks per wave
@@ -87,7 +91,7 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
   constexpr bool WLDS = (P::KPL == 8);
 
   extern __shared__ __align__(16) char smem[];
-  const int M = a.M, MB = M / 32;
+  const int M = MBC ? 32 * MBC : a.M, MB = M / 32;
   const int wtotal = 4 * D * D + 2 * D * M;
   // LDS carve-up: [weights (BF16 only)] [b1 M] [b2 D] [table 64*D] [pool scratch: 64 float2 per wave]
   elem_t* wl = reinterpret_cast<elem_t*>(smem);
@@ -124,9 +128,7 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
   const int64_t ntiles = SPAN ? 2 * E : 2 * ((E + cpb - 1) / cpb);
   const float sc = a.score_scale;  // log2(e)/sqrt(dh)
 
-  // valid (query row qb*32+lr, key row kb*32+tile_idx(r, h)) pairs as bit r of okbits[qb][kb];
-  // use_mask (uniform) is false when every pair of a tile is valid
-  const bool use_mask = SPAN ? (n < 64) : (a.masked != 0);
+  // valid (query row qb*32+lr, key row kb*32+tile_idx(r, h)) pairs as bit r of okbits[qb][kb]
   uint32_t okbits[NBR][NBR];
 #pragma unroll
   for (int qb = 0; qb < NBR; ++qb)
@@ -271,7 +273,7 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
 #pragma unroll
           for (int kb = 0; kb < NBR; ++kb) {
             st[kb] = P::template scores_packed<DH>(kp[kb][j], qp[qb][j], f32x16{});
-            if (use_mask) {
+            if constexpr (MASKED) {
 #pragma unroll
               for (int r = 0; r < 16; ++r)
                 if (!((okbits[qb][kb] >> r) & 1u)) st[kb][r] = -INFINITY;
@@ -334,7 +336,7 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
       for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
         for (int s = 0; s < ST; ++s) xo[rb][ib][s] = P::op(x[rb][ib], s);
-#pragma unroll 2
+#pragma unroll
     for (int c = 0; c < MB; ++c) {
       float bias[16];
 #pragma unroll
@@ -432,17 +434,32 @@ __global__ void k_symmetrise(const int64_t* __restrict__ E_dev, int64_t E_host, 
 }
 
 // ------------------------------------------------------------------ dispatch
-template <class P, int D, int DH, bool SPAN>
-static int32_t launch_layer_t(const FwdArgs& a, int num_cus, hipStream_t st) {
+template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED>
+static int32_t launch_layer_m(const FwdArgs& a, int num_cus, hipStream_t st) {
   const size_t wbytes = (P::KPL == 8) ? (size_t)(4 * D * D + 2 * D * a.M) * sizeof(typename P::elem_t) : 0;
   constexpr int threads = fwd_threads<P, SPAN>();
   const size_t lds = wbytes + (size_t)(a.M + D) * 4 + (a.first ? 64 * D * 4 : 0) + (threads / 64) * 64 * sizeof(float2);
-  auto kern = k_fwd_layer<P, D, DH, SPAN>;
+  auto kern = k_fwd_layer<P, D, DH, SPAN, MBC, MASKED>;
   TDO_TRY(allow_full_lds((const void*)kern));
   const int blocks = num_cus * a.blocks_per_cu;
   hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, st, a);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
+}
+
+// the BF16 width-64 kernels with the feed-forward width 4 x 64 fixed at compile time
+template <class P, int D, int DH, bool SPAN, bool MASKED>
+static int32_t launch_layer_k(const FwdArgs& a, int num_cus, hipStream_t st) {
+  if constexpr (P::KPL == 8 && D == 64)
+    if (a.M == 256) return launch_layer_m<P, D, DH, SPAN, 8, MASKED>(a, num_cus, st);
+  return launch_layer_m<P, D, DH, SPAN, 0, MASKED>(a, num_cus, st);
+}
+
+// masking is needed with several configurations per block, or padding rows of a spanning pass
+template <class P, int D, int DH, bool SPAN>
+static int32_t launch_layer_t(const FwdArgs& a, int num_cus, hipStream_t st) {
+  const bool masked = SPAN ? (a.n < 64) : (a.masked != 0);
+  return masked ? launch_layer_k<P, D, DH, SPAN, true>(a, num_cus, st) : launch_layer_k<P, D, DH, SPAN, false>(a, num_cus, st);
 }
 
 template <class P>
