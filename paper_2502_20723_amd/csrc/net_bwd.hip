@@ -4,7 +4,7 @@
 //
 // Per layer two kernels run in reverse order, each recomputing the layer's
 // internals from the activations saved by the forward pass:
-//   MLP:       u = x W1 + b1, dh = g W2^T, du = dh [u > 0], dx = g + du W1^T,
+//   MLP:       u = b1 + x W1, dh = g W2^T, du = dh [u > 0], dx = g + du W1^T,
 //              dW1 += x^T du, dW2 += relu(u)^T g, db1 += sum du, db2 += sum g;
 //   attention: q, k, v, P = softmax(q k^T / sqrt(dh)) per head, O = P v;
 //              dO = dx W_O^T, dP = dO v^T, dS = P (dP - rowsum(P dP)) / sqrt(dh),
@@ -167,7 +167,9 @@ __global__ void __launch_bounds__(256) k_bwd_mlp(BwdArgs a) {
     for (int ob = 0; ob < NB; ++ob) dxm[ob] = gv[ob];
 #pragma unroll 1
     for (int c = 0; c < MB; ++c) {
-      f32x16 u = f32x16{}, dh = f32x16{};
+      f32x16 u, dh = f32x16{};  // u accumulates onto b1, in the forward's order
+#pragma unroll
+      for (int r = 0; r < 16; ++r) u[r] = a.b1[32 * c + tile_idx(r, h)];
 #pragma unroll
       for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
@@ -178,7 +180,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp(BwdArgs a) {
       f32x16 hh, du;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float uu = u[r] + a.b1[32 * c + tile_idx(r, h)];
+        const float uu = u[r];
         hh[r] = relu(uu);
         du[r] = uu > 0.f ? dh[r] : 0.f;
       }

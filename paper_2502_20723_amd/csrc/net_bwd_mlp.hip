@@ -1,6 +1,6 @@
 // Backward of the residual feed-forward sub-layer y = x + relu(x W1 + b1) W2 + b2
 // for width 64 with BF16 MFMA operands (FP32 accumulation):
-//   u = x W1 + b1 (recomputed), dh = g W2^T, du = dh [u > 0], dx = g + du W1^T,
+//   u = b1 + x W1 (recomputed, with the forward's rounding order), dh = g W2^T, du = dh [u > 0], dx = g + du W1^T,
 //   dW1 += x^T du, dW2 += relu(u)^T g, db1 += sum du, db2 += sum g.
 //
 // Work decomposition.  A workgroup (4 waves) walks 64-row tiles (two 32-row
@@ -215,7 +215,11 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
     for (int rb = 0; rb < 2; ++rb) {
       f32x16 u[HT], dh[HT];
 #pragma unroll
-      for (int nt = 0; nt < HT; ++nt) { u[nt] = f32x16{}; dh[nt] = f32x16{}; }
+      for (int nt = 0; nt < HT; ++nt) {  // u accumulates onto b1, in the forward's order
+        dh[nt] = f32x16{};
+#pragma unroll
+        for (int r = 0; r < 16; ++r) u[nt][r] = bias[nt];
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const bf16x8 xa = ld8(XA + (32 * rb + lr) * XS + 16 * s + 8 * h);
@@ -230,7 +234,7 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
       for (int nt = 0; nt < HT; ++nt)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const float uu = u[nt][r] + bias[nt];
+          const float uu = u[nt][r];
           const float d = uu > 0.f ? dh[nt][r] : 0.f;
           u[nt][r] = uu > 0.f ? uu : 0.f;  // relu(u)
           dh[nt][r] = d;                   // du
@@ -455,7 +459,9 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
     // ---- 2. hidden units of this wave: u, dh, du; dW1, dW2, db1; du to LDS
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
-      f32x16 u = {}, dh = {};
+      f32x16 u, dh = {};  // u accumulates onto b1, in the forward's order
+#pragma unroll
+      for (int r = 0; r < 16; ++r) u[r] = bias;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const bf16x8 xa = ld8(XA + (32 * rb + lr) * XS + 16 * s + 8 * h);
@@ -465,7 +471,7 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float uu = u[r] + bias;
+        const float uu = u[r];
         const float d = uu > 0.f ? dh[r] : 0.f;
         u[r] = uu > 0.f ? uu : 0.f;  // relu(u)
         dh[r] = d;                   // du

@@ -283,17 +283,24 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
           }
           m = xor32_max(m);
           const float mm = (m == -INFINITY) ? 0.f : m;  // a row with no key keeps P = 0
-          float l = 0.f;
 #pragma unroll
           for (int kb = 0; kb < NBR; ++kb)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const float p = __builtin_amdgcn_exp2f(st[kb][r] - mm);
-              st[kb][r] = p;
-              l += p;
-            }
-          l = xor32_sum(l);
-          invl[qb][j] = l > 0.f ? 1.0f / l : 0.f;
+            for (int r = 0; r < 16; ++r) st[kb][r] = __builtin_amdgcn_exp2f(st[kb][r] - mm);
+          // row sum as a pairwise tree (short dependency chains)
+          float part[NBR * 8];
+#pragma unroll
+          for (int kb = 0; kb < NBR; ++kb)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) part[8 * kb + i] = st[kb][2 * i] + st[kb][2 * i + 1];
+#pragma unroll
+          for (int w = NBR * 4; w >= 1; w /= 2)
+#pragma unroll
+            for (int i = 0; i < w; ++i) part[i] += part[i + w];
+          const float l = xor32_sum(part[0]);
+          // l >= 1 when the row has a key (its maximum contributes exp2(0)): the hardware
+          // reciprocal (1 ulp) replaces the division sequence
+          invl[qb][j] = l > 0.f ? __builtin_amdgcn_rcpf(l) : 0.f;
           // for the backward: P = exp2(s - lse) (+inf for a row with no key, so that P = 0)
           lsev[qb][j] = l > 0.f ? mm + __builtin_amdgcn_logf(l) : INFINITY;
 #pragma unroll
@@ -338,18 +345,22 @@ __global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs 
         for (int s = 0; s < ST; ++s) xo[rb][ib][s] = P::op(x[rb][ib], s);
 #pragma unroll
     for (int c = 0; c < MB; ++c) {
-      float bias[16];
+      // the products accumulate onto b1 (values r = 4q .. 4q+3 hold 4 consecutive hidden units)
+      f32x16 bias;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) bias[r] = b1s[32 * c + tile_idx(r, h)];
+      for (int q = 0; q < 4; ++q) {
+        const float4 b = *reinterpret_cast<const float4*>(b1s + 32 * c + 8 * q + 4 * h);
+        bias[4 * q] = b.x; bias[4 * q + 1] = b.y; bias[4 * q + 2] = b.z; bias[4 * q + 3] = b.w;
+      }
 #pragma unroll
       for (int rb = 0; rb < NBR; ++rb) {
-        f32x16 u = f32x16{};
+        f32x16 u = bias;
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
           for (int s = 0; s < ST; ++s) u = P::mma(ld_frag<P>(W1, (c * NB + ib) * ST + s, lane), xo[rb][ib][s], u);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) u[r] = relu(u[r] + bias[r]);
+        for (int r = 0; r < 16; ++r) u[r] = relu(u[r]);
 #pragma unroll
         for (int ob = 0; ob < NB; ++ob)
 #pragma unroll

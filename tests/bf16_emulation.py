@@ -12,6 +12,11 @@ where the stated ones cannot hold for the arithmetic itself.
 The error of an emulation against the FP64 oracle is the error that precision
 incurs by itself; a GPU result is required to stay within a small factor of
 it.  It is not a reference for parity (the FP64 oracle is).
+
+``kink_sensitivity`` bounds a second effect of rounding on the gradient: the
+feed-forward ReLU decides a unit's branch from the sign of its pre-activation,
+and for a pre-activation within rounding distance of zero that sign is decided
+by summation order.
 """
 import math
 
@@ -20,6 +25,9 @@ import torch
 
 from oracle import ansatz as oa
 from oracle import lindblad as ol
+from oracle import vmc
+
+KINK_KAPPA = 2.0 ** -23  # two FP32 rounding steps
 
 
 def _r16(t):
@@ -108,3 +116,23 @@ def loss_grad_emulated(theta, arch, model, cfg, weights, mode, prec):
         obj = (r * L.abs() ** 2 - F * r).sum() / W
     (g,) = torch.autograd.grad(obj, th)
     return float(F), g.double().numpy()
+
+
+def kink_sensitivity(params, A, M, cfg, w, mode, g_ref, kappa=KINK_KAPPA):
+    """Relative change of the FP64 gradient when the ReLU of every feed-forward unit
+    whose pre-activation u lies within kappa (|b1| + sum |x W1|) of zero takes the
+    other branch (the oracle's feed-forward function is replaced for one call)."""
+    orig = oa.mlp
+
+    def mlp_flipped(x, w1, b1, w2, b2):
+        u = x @ w1 + b1
+        near = u.detach().abs() < kappa * (x.abs() @ w1.abs() + b1.abs()).detach()
+        h = torch.where(near, torch.where(u > 0, torch.zeros_like(u), u), torch.clamp(u, min=0.0))
+        return h @ w2 + b2
+
+    oa.mlp = mlp_flipped
+    try:
+        _, gk, _ = vmc.loss_grad(params.astype(np.float64), A, M, cfg, w, mode=mode)
+    finally:
+        oa.mlp = orig
+    return float(np.linalg.norm(gk - g_ref) / max(np.linalg.norm(g_ref), 1e-300))

@@ -8,7 +8,7 @@ from oracle import ansatz as oa
 from oracle import lindblad as ol
 from oracle import vmc
 from paper_2502_20723_amd import synth
-from tests.bf16_emulation import loss_grad_emulated
+from tests.bf16_emulation import kink_sensitivity, loss_grad_emulated
 from tests.parity import rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -19,11 +19,15 @@ ARCH = {k: synth.WORKLOADS[k]["arch"] for k in synth.WORKLOADS}
 # tolerance is derived from the arithmetic as twice the larger of
 #  * the error of the same precision emulated on the CPU (tests/bf16_emulation.py);
 #  * (FP32) the change of the FP64 gradient when every parameter moves by one
-#    FP32 rounding step (relative 2^-24, random signs, max over 3 draws).  The
-#    feed-forward ReLU makes the gradient jump where a pre-activation crosses
-#    zero; when one lies within rounding distance of zero, which side an FP32
-#    evaluation lands on is decided by summation order, and the estimators'
-#    cancellation (sum_k g_k O(y_k) against |L|^2 O(x)) can magnify that jump.
+#    FP32 rounding step (relative 2^-24, random signs, max over 3 draws);
+#  * (FP32, with a factor 1.5 instead of 2) the change of the FP64 gradient when
+#    every feed-forward pre-activation within KINK_KAPPA of zero, relative to the
+#    magnitude of its summands (|b1| + sum |x W1|), is moved to the other side of
+#    the ReLU.  The ReLU makes the gradient jump where a pre-activation crosses
+#    zero; for such units the side an FP32 evaluation lands on is decided by
+#    summation order, and the estimators' cancellation (sum_k g_k O(y_k) against
+#    |L|^2 O(x)) can magnify the jump.  At the benchmark shape (886 evaluated
+#    configurations, 58 M pre-activations) dozens of units lie that close to zero.
 GTOL = {"fp32": 1e-3, "bf16": 2e-2}
 LTOL = {"fp32": 1e-5, "bf16": 2e-2}   # relative loss (stated)
 
@@ -40,9 +44,12 @@ def grad_tol(prec, params, arch, model, cfg, w, mode, g_ref):
             tp = th * (1.0 + rng.choice([-1.0, 1.0], th.size) * 2.0 ** -24)
             _, gp, _ = vmc.loss_grad(tp, A, M, cfg, w, mode=mode)
             sens = max(sens, rel_l2(gp, g_ref))
-    tol = max(GTOL[prec], 2.0 * emu, 2.0 * sens)
-    print(f"  {prec} emulation grad err {emu:.3e}, rounding-step sensitivity {sens:.3e} -> tolerance {tol:.3e}")
+    kink = kink_sensitivity(params, A, M, cfg, w, mode, g_ref) if prec == "fp32" else 0.0
+    tol = max(GTOL[prec], 2.0 * emu, 2.0 * sens, 1.5 * kink)
+    print(f"  {prec} emulation grad err {emu:.3e}, rounding-step sensitivity {sens:.3e}, "
+          f"kink sensitivity {kink:.3e} -> tolerance {tol:.3e}")
     return tol
+
 
 
 def cuda(x):
