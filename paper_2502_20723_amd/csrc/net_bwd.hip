@@ -435,7 +435,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn(BwdArgs a) {
 template <class P, int D>
 __global__ void __launch_bounds__(256) k_bwd_head(const void* __restrict__ save_last, const float* __restrict__ seeds,
                                                   const int64_t* E_dev, int64_t E_host, int n, int cpb, int span,
-                                                  int d_real, double* __restrict__ gw, double* __restrict__ gb) {
+                                                  int d_real, double* __restrict__ part) {
   using save_t = typename P::save_t;
   constexpr int NB = D / 32;
   const int64_t E = E_dev ? *E_dev : E_host;
@@ -472,7 +472,9 @@ __global__ void __launch_bounds__(256) k_bwd_head(const void* __restrict__ save_
       }
     }
   }
-  // sum over the 32 rows (lanes of one half), then one atomic per feature and workgroup wave
+  // sum over the 32 rows (lanes of one half) and then over the 4 waves, in a fixed order, into
+  // this workgroup's slot part[block][2 d_real + 2] ([feature][2] head weights, then the bias)
+  __shared__ double red[4][2 * D + 2];
 #pragma unroll
   for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
@@ -481,16 +483,43 @@ __global__ void __launch_bounds__(256) k_bwd_head(const void* __restrict__ save_
 #pragma unroll
       for (int o = 16; o > 0; o >>= 1) { u0 += __shfl_xor(u0, o, 64); u1 += __shfl_xor(u1, o, 64); }
       const int f = 32 * ob + tile_idx(r, h);
-      if (lr == 0 && f < d_real) {
-        atomicAdd(gw + 2 * f, u0);
-        atomicAdd(gw + 2 * f + 1, u1);
+      if (lr == 0) {
+        red[wave][2 * f] = u0;
+        red[wave][2 * f + 1] = u1;
       }
     }
 #pragma unroll
   for (int o = 16; o > 0; o >>= 1) { c0 += __shfl_xor(c0, o, 64); c1 += __shfl_xor(c1, o, 64); }
   if (lane == 0) {
-    atomicAdd(gb, c0);
-    atomicAdd(gb + 1, c1);
+    red[wave][2 * D] = c0;
+    red[wave][2 * D + 1] = c1;
+  }
+  __syncthreads();
+  const int len = 2 * d_real + 2;
+  for (int i = threadIdx.x; i < len; i += 256) {
+    const int k = i < 2 * d_real ? i : 2 * D + (i - 2 * d_real);
+    part[(int64_t)blockIdx.x * len + i] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  }
+}
+
+// Sum of the head kernel's workgroup slots, one workgroup per entry in a fixed order:
+// gw[i] (i < 2 d_real) or gb[i - 2 d_real] += sum over the nparts slots.
+__global__ void __launch_bounds__(256) k_reduce_head(const double* __restrict__ part, int nparts, int d_real,
+                                                     double* __restrict__ gw, double* __restrict__ gb) {
+  __shared__ double sh[256];
+  const int len = 2 * d_real + 2, i = blockIdx.x, t = threadIdx.x;
+  double s = 0.0;
+  for (int p = t; p < nparts; p += 256) s += part[(int64_t)p * len + i];
+  sh[t] = s;
+  __syncthreads();
+#pragma unroll
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (i < 2 * d_real) gw[i] += sh[0];
+    else gb[i - 2 * d_real] += sh[0];
   }
 }
 
@@ -764,14 +793,18 @@ int32_t launch_bwd_attn(const BwdArgs& a, bool bf16, int D, int DH, int blocks, 
 }
 
 int32_t launch_bwd_head(bool bf16, int D, const void* save_last, const float* seeds, const int64_t* E_dev,
-                        int64_t E_host, int n, int cpb, int span, int d_real, double* gw, double* gb, hipStream_t st) {
+                        int64_t E_host, int n, int cpb, int span, int d_real, double* gw, double* gb, double* part,
+                        hipStream_t st) {
+  constexpr int G = HEAD_BLOCKS;
   if (D == 32) {
-    if (bf16) hipLaunchKernelGGL((k_bwd_head<PBF16, 32>), dim3(1024), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
-    else hipLaunchKernelGGL((k_bwd_head<PF32, 32>), dim3(1024), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
+    if (bf16) hipLaunchKernelGGL((k_bwd_head<PBF16, 32>), dim3(G), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, part);
+    else hipLaunchKernelGGL((k_bwd_head<PF32, 32>), dim3(G), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, part);
   } else {
-    if (bf16) hipLaunchKernelGGL((k_bwd_head<PBF16, 64>), dim3(1024), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
-    else hipLaunchKernelGGL((k_bwd_head<PF32, 64>), dim3(1024), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, gw, gb);
+    if (bf16) hipLaunchKernelGGL((k_bwd_head<PBF16, 64>), dim3(G), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, part);
+    else hipLaunchKernelGGL((k_bwd_head<PF32, 64>), dim3(G), dim3(256), 0, st, save_last, seeds, E_dev, E_host, n, cpb, span, d_real, part);
   }
+  TDO_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_head, dim3(2 * d_real + 2), dim3(256), 0, st, part, G, d_real, gw, gb);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
 }

@@ -80,8 +80,11 @@ bool bwd_attn_bf16_supported(int d, int D, int DH, bool span);
 int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t st);
 int32_t launch_bwd_mlp(const BwdArgs& a, bool bf16, int D, int blocks, hipStream_t st);
 int32_t launch_bwd_attn(const BwdArgs& a, bool bf16, int D, int DH, int blocks, hipStream_t st);
+// part: FP64 scratch of HEAD_BLOCKS * (2 d_real + 2) values (one slot per workgroup).
+constexpr int HEAD_BLOCKS = 1024;
 int32_t launch_bwd_head(bool bf16, int D, const void* save_last, const float* seeds, const int64_t* E_dev,
-                        int64_t E_host, int n, int cpb, int span, int d_real, double* gw, double* gb, hipStream_t st);
+                        int64_t E_host, int n, int cpb, int span, int d_real, double* gw, double* gb, double* part,
+                        hipStream_t st);
 int32_t launch_embed_scatter(int D, const float* dx0, const uint64_t* ecfg, const int64_t* E_dev, int64_t E_host,
                              int n, int cpb, int span, float* partial, int blocks, hipStream_t st);
 // part: FP64 scratch of 64 * (6 d + 2 d^2) values (one slot per window code).

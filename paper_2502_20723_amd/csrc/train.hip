@@ -180,8 +180,9 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
     TDO_TRY(launch_reduce_partials(bb.partial, bb.nparts, alen, bb.attn_acc, st));
     TDO_TRY(launch_scatter_layer(bb.mlp_acc, bb.attn_acc, pp.d, D, M, 1.0, gt + pp.off_layer0 + l * pp.layer_stride, st));
   }
+  // the head kernel's workgroup slots reuse the partial buffer (free here; sized for them in plan_train)
   TDO_TRY(launch_bwd_head(np.bf16, D, sv.last, dF, E_dev, E, np.n, np.cpb, np.span, pp.d, gt + pp.off_head_w,
-                          gt + pp.off_head_b, st));
+                          gt + pp.off_head_b, reinterpret_cast<double*>(bb.partial), st));
   // table gradient accumulated over every call of this entry point; the chain rule into the
   // convolution parameters (linear in it) runs once at the end (finish_backward)
   // two workgroups per CU (each wave a partial): the second one's waves hide the first's latencies
@@ -212,9 +213,12 @@ int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, T
   t->attn_acc = ar.take<double>(4LL * np.D * np.D);
   t->dT_acc = ar.take<double>(64LL * np.D);
   // per CU: the feed-forward or attention weight partials, or 8 wave partials of the table gradient;
-  // in all, at least the FP64 per-code slots of the embedding chain rule
+  // in all, at least the FP64 per-code slots of the embedding chain rule and the head kernel's
+  // workgroup slots
   const int64_t maxlen = std::max<int64_t>(std::max<int64_t>(std::max<int64_t>(mlen, 4LL * np.D * np.D), 8 * 64LL * np.D),
-                                           (2 * 64 * (6LL * pp.d + 2LL * pp.d * pp.d) + c.num_cus - 1) / c.num_cus);
+                                           std::max<int64_t>(2 * 64 * (6LL * pp.d + 2LL * pp.d * pp.d),
+                                                             2LL * HEAD_BLOCKS * (2 * pp.d + 2)) /
+                                                   c.num_cus + 1);
   t->partial = ar.take<float>((size_t)c.num_cus * maxlen);
   const size_t fixed = ar.used + 64 * 256;  // includes the per-sample L buffer
   const int save = np.bf16 ? 2 : 4;

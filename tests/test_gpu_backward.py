@@ -173,9 +173,9 @@ def test_gradient_matches_finite_differences(gpu):
                                       ("batched_uneven", 40, 200), ("batched_uneven", 64, 64)])
 def test_bf16_gradient_reproducible(gpu, name, n, B):
     """BF16, width 64 (the register-gradient backward kernels, also for chains that
-    span two blocks): repeated calls give the same loss and gradient.  Every weight
-    gradient is formed by fixed owners in a fixed order; only the output head's FP64
-    sums use atomics (order-dependent in the last bits)."""
+    span two blocks): repeated calls give bit-identical loss and gradient.  Every
+    gradient, the output head's included, is formed by fixed owners and summed in a
+    fixed order (no atomics)."""
     arch = ARCH[name]
     model = model_of(name, n)
     params = cuda(synth.params(arch, 41, "mid"))
@@ -184,8 +184,6 @@ def test_bf16_gradient_reproducible(gpu, name, n, B):
     runs = [ctx.loss_grad(arch, params, model, cfg, None, "bf16", "B") for _ in range(3)]
     torch.cuda.synchronize()
     l0, g0 = float(runs[0][0][0]), runs[0][1]
-    nh = 2 * arch["d"] + 2  # head_w, head_b (the last parameters)
     for l, g, _ in runs[1:]:
         assert float(l[0]) == l0
-        assert torch.equal(g[:-nh], g0[:-nh])
-        assert rel_l2(g[-nh:].cpu().numpy(), g0[-nh:].cpu().numpy()) < 1e-13
+        assert torch.equal(g, g0)

@@ -51,9 +51,9 @@ def test_matches_oracle_per_problem(gpu):
 
 
 # Run-to-run agreement of the gradient: the FP32 kernels add weight gradients into
-# LDS with FP32 atomics whose order varies from run to run, and the head gradient
-# is added with FP64 atomics (both precisions).
-REPEAT_TOL = {"fp32": 1e-5, "bf16": 1e-5}
+# LDS with FP32 atomics whose order varies from run to run; the BF16 kernels of
+# width 64 have no atomics (bit-identical).
+REPEAT_TOL = {"fp32": 1e-5, "bf16": 0.0}
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -75,7 +75,7 @@ def test_equals_single_problem_calls_and_replays(gpu, prec):
             s.synchronize()
             for i in range(8):
                 assert abs(float(loss[i]) - float(ref[i][0][0])) <= 1e-12 * abs(float(ref[i][0][0])), (call, i)
-                assert rel_l2(grads[i].cpu().numpy(), ref[i][1].cpu().numpy()) < REPEAT_TOL[prec], (call, i)
+                assert rel_l2(grads[i].cpu().numpy(), ref[i][1].cpu().numpy()) <= REPEAT_TOL[prec], (call, i)
         # change the parameters of problem 3 in place: the replay must see them
         pt[3].mul_(0.5)
         loss, grads = ctx.loss_grad_batched(ARCH, pt, models, ct, None, prec, "B", out=out)
@@ -84,7 +84,7 @@ def test_equals_single_problem_calls_and_replays(gpu, prec):
     l3, g3, _ = ctx.loss_grad(ARCH, pt[3], models[3], ct[3], None, prec, "B")
     torch.cuda.synchronize()
     assert abs(float(loss[3]) - float(l3[0])) <= 1e-12 * abs(float(l3[0]))
-    assert rel_l2(grads[3].cpu().numpy(), g3.cpu().numpy()) < REPEAT_TOL[prec]
+    assert rel_l2(grads[3].cpu().numpy(), g3.cpu().numpy()) <= REPEAT_TOL[prec]
 
 
 def test_full_size_workload_sampled(gpu):

@@ -45,4 +45,4 @@ def test_high_bits_ignored(gpu, name, n, B):
         nh = 2 * arch["d"] + 2
         scale = float(g0.abs().max())
         assert float((g0[:-nh] - g1[:-nh]).abs().max()) <= tol * scale
-        assert float((g0[-nh:] - g1[-nh:]).abs().max()) <= 1e-12 * scale + tol * scale
+        assert float((g0[-nh:] - g1[-nh:]).abs().max()) <= tol * scale
