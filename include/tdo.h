@@ -147,7 +147,9 @@ int32_t tdo_log_rho_vjp(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *par
  *   weights are the exact |rho|^2 of all configurations.
  * grad_mode 1 ("A"): gradient of the weighted mean with w held fixed.
  * loss: device double [1]; grad: device double [P]; lloc_out: device float
- * [B][2] or NULL.  Reductions over samples are in FP64. */
+ * [B][2] or NULL.  Reductions over samples are in FP64.
+ * B >= 1 (a mean over no samples is rejected with TDO_EINVAL); the weights are
+ * not inspected: their sum must be positive, as loss and gradient divide by it. */
 int32_t tdo_loss_grad(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params,
                       const tdo_model_t *model, const uint64_t *cfg, int64_t B,
                       const double *weights, tdo_prec_t prec, int32_t grad_mode, double *loss,

@@ -3,8 +3,8 @@
 // (Eq. attn-head-appendix), for width 64 with BF16 MFMA operands and FP32
 // accumulation, chains of n <= 32 sites (configurations never span blocks):
 //   dO = g W_O^T;  per head: P = exp2(S - lse) from the log2 row normalisers lse the forward
-//   saved (the scores S here are the same bits as there), dP = dO V^T,
-//   dS = P (dP - rowsum(P dP)) / sqrt(dh),
+//   saved (the scores S here are the same bits as there), dP' = (dO / sqrt(dh)) V^T,
+//   dS = P (dP' - rowsum(P dP')) (= P (dP - rowsum(P dP)) / sqrt(dh)),
 //   dQ = dS K, dK = dS^T Q, dV = P^T dO;  dx = g + dQ Wq^T + dK Wk^T + dV Wv^T;
 //   dW_O += O^T g, dWq += x^T dQ, dWk += x^T dK, dWv += x^T dV.
 //
@@ -224,6 +224,9 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
           OR = mfma16(wo, go[ib][s], OR);
           OF = mfma16(go[ib][s], wo, OF);
         }
+      // dO as the score operand of dP carries the factor 1/sqrt(dh) of dS
+#pragma unroll
+      for (int r = 0; r < 16; ++r) OR[r] *= isd;
 #pragma unroll
       for (int j = 0; j < HPB; ++j) {
         VRp[j] = PBF16::pack_head<DH>(VR, j);
@@ -257,7 +260,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       }
       dl = xor32_sum(dl);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) dpq[r] = sq[r] * (dpq[r] - dl) * isd;  // dS
+      for (int r = 0; r < 16; ++r) dpq[r] = sq[r] * (dpq[r] - dl);  // dS (dP carries 1/sqrt(dh))
       bf16x8 Pq[ST], Sq[ST];
 #pragma unroll
       for (int s = 0; s < ST; ++s) { Pq[s] = cvt8(sq, s); Sq[s] = cvt8(dpq, s); }
@@ -513,6 +516,9 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
             OR = mfma16(wo, go[rb][ib][s], OR);
             OF = mfma16(go[rb][ib][s], wo, OF);
           }
+        // dO as the score operand of dP carries the factor 1/sqrt(dh) of dS
+#pragma unroll
+        for (int r = 0; r < 16; ++r) OR[r] *= isd;
 #pragma unroll
         for (int j = 0; j < HPB; ++j) {
           VRp[rb][j] = PBF16::pack_head<DH>(VR, j);
@@ -555,7 +561,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) dpq[kb][r] = sq[kb][r] * (dpq[kb][r] - dl) * isd;  // dS
+          for (int r = 0; r < 16; ++r) dpq[kb][r] = sq[kb][r] * (dpq[kb][r] - dl);  // dS (dP carries 1/sqrt(dh))
           bf16x8 Pq[ST], Sq[ST];
 #pragma unroll
           for (int s = 0; s < ST; ++s) { Pq[s] = cvt8(sq[kb], s); Sq[s] = cvt8(dpq[kb], s); }
