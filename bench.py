@@ -104,6 +104,8 @@ def main():
                     help="skip the batched-workload and sampler measurements (BF16, reported beside the headline)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one elementwise copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--lindblad-only", action="store_true",
+                    help="measure only tdo_connected and tdo_local_lindbladian (HBM-bound) and print their line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the samples shard "
@@ -145,6 +147,12 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: calibration copy of {args.copy_calibration_mib} MiB done")
         del src, dst
+
+    if args.lindblad_only:
+        print(json.dumps({"metric": "Lindbladian rows and L_loc, algorithmic HBM GB/s",
+                          "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}), flush=True)
+        ctx.close()
+        return
 
     results = {}
     stream = torch.cuda.current_stream()
@@ -209,7 +217,8 @@ def main():
     extras = None
     if not args.no_extras:
         extras = {"batched_uneven": bench_batched(ctx, tdo, synth, args.steps),
-                  "sampler": bench_sampler(ctx, arch, params, n, synth)}
+                  "sampler": bench_sampler(ctx, arch, params, n, synth),
+                  "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -303,6 +312,53 @@ def bench_sampler(ctx, arch, params, n, synth):
     props = C * 2 * n
     log(f"bench: sampler {C} chains x {2 * n} proposals in {ms:.1f} ms: {props / ms * 1e3 / 1e6:.2f} M proposals/s")
     return {"value": props / (ms / 1e3), "unit": "proposals/s", "chains": C, "sweeps": 1, "ms": ms, "dtype": "bf16"}
+
+
+def bench_lindblad(ctx, tdo, model, synth, steps, B=1 << 20):
+    """tdo_connected and tdo_local_lindbladian on 2^20 samples of the n = 32 Ising
+    chain (kmax = 3n + 1): time per call and algorithmic HBM bytes over it, against
+    the 8 TB/s peak.  Algorithmic bytes per sample: rows 16 (read x) + 4 (count) +
+    24 per entry (written y and coefficient; slots beyond the count are not written);
+    L_loc 8 + 4 + 8 (log rho(x), count, result) + 16 per entry (coefficient and
+    log rho(y) read).  The library is called directly on preallocated outputs (the
+    binding's zero-filled output tensors would add fill kernels to the timing)."""
+    import ctypes
+
+    import torch
+    n = model["n"]
+    kmax = 3 * n + 1
+    cfg = torch.from_numpy(synth.configs(n, B, 5000)).cuda()
+    gen = torch.Generator(device="cuda").manual_seed(5001)
+    lr_x = 0.1 * torch.randn((B, 2), generator=gen, device="cuda")
+    lr_conn = 0.1 * torch.randn((B, kmax, 2), generator=gen, device="cuda")
+    conn, mel, ncon = ctx.connected(model, cfg, kmax)
+    out = ctx.local_lindbladian(lr_x, mel, ncon, lr_conn)
+    torch.cuda.synchronize()
+    entries = int(ncon.sum().item())
+    res = {}
+    L, P, st, mt = tdo.lib(), tdo._ptr, tdo._stream, tdo.model_t(model)
+
+    def rows():
+        tdo._check(L.tdo_connected(ctx.h, ctypes.byref(mt), P(cfg), B, kmax, P(conn), P(mel), P(ncon), st()))
+
+    def lloc():
+        tdo._check(L.tdo_local_lindbladian(ctx.h, B, P(lr_x), P(mel), P(ncon), kmax, P(lr_conn), P(out), st()))
+
+    for name, call, nbytes in (("connected", rows, B * 20 + entries * 24),
+                               ("local_lindbladian", lloc, B * 20 + entries * 16)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(max(steps, 1)):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / max(steps, 1)
+        gbs = nbytes / (ms / 1e3) / 1e9
+        res[name] = {"ms": ms, "bytes": nbytes, "GB/s": gbs, "frac_of_8TB/s": gbs / 8000.0}
+        log(f"bench: {name} B={B} ({entries} entries): {ms:.3f} ms, {gbs:.0f} GB/s algorithmic "
+            f"({100 * gbs / 8000:.1f}% of 8 TB/s)")
+    del conn, mel, ncon, out, lr_conn
+    return {"B": B, "n": n, "kmax": kmax, "entries": entries, "kernels": res}
 
 
 def cpu_baseline(arch, model, params_np, cfg_np):

@@ -59,6 +59,32 @@ __device__ __forceinline__ bool lin2_is_zero(double a, int p, double b, int q) {
   return x1 == x2 && e1 == e2;
 }
 
+// The model's fields as values in (scalar) registers.  Read straight from the kernel argument,
+// a per-lane choice between two fields (e.g. Jx - Jy or Jx + Jy by the bond's spins) is
+// compiled into one load from a per-lane address in the argument segment, waited on inside
+// the slot loop; readfirstlane makes each field a register value, so the choice is a select.
+__device__ __forceinline__ int in_reg(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double in_reg(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+// Wait for every vector memory operation of the wave (s_waitcnt vmcnt(0); the expcnt and
+// lgkmcnt fields of the gfx9 encoding at their maxima, i.e. no wait on them).  Placed right
+// after a batch of loads, it keeps the compiler from waiting for all outstanding stores at the
+// first use of those loads inside a loop (the counter is shared and in order).
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ __forceinline__ ModelDev in_regs(const ModelDev& m) {
+  ModelDev r;
+  r.kind = in_reg(m.kind); r.n = in_reg(m.n); r.nslots = in_reg(m.nslots); r.has_fields = in_reg(m.has_fields);
+  r.gamma_ok = in_reg(m.gamma_ok); r.hmove_eq = in_reg(m.hmove_eq); r.hmove_ne = in_reg(m.hmove_ne);
+  r.gam = in_reg(m.gam); r.gam2 = in_reg(m.gam2); r.V4 = in_reg(m.V4); r.g2 = in_reg(m.g2); r.Jz = in_reg(m.Jz);
+  r.jm = in_reg(m.jm); r.jp = in_reg(m.jp); r.Bx = in_reg(m.Bx); r.By = in_reg(m.By); r.Bz = in_reg(m.Bz);
+  return r;
+}
+
 __device__ bool slot_entry(const ModelDev& m, uint64_t a, uint64_t b, int s, uint64_t& ya,
                            uint64_t& yb, float& cre, float& cim) {
   const int n = m.n;
@@ -102,8 +128,10 @@ __device__ bool slot_entry(const ModelDev& m, uint64_t a, uint64_t b, int s, uin
       const int j = (i + 1) % n;
       const bool eq = ((x >> i) & 1ull) == ((x >> j) & 1ull);
       flip = (1ull << i) | (1ull << j);
-      c = eq ? m.jm : m.jp;  // Jx - Jy s_i s_j
-      ok = eq ? m.hmove_eq : m.hmove_ne;
+      // choices between two fields go through in_reg, so that they stay selects of values
+      // (not one load from a per-lane address)
+      c = eq ? in_reg(m.jm) : in_reg(m.jp);  // Jx - Jy s_i s_j
+      ok = eq ? in_reg(m.hmove_eq) : in_reg(m.hmove_ne);
     }
     if (on_a) ya = (a ^ flip) & mask; else yb = (b ^ flip) & mask;
     cre = 0.0f;
@@ -134,41 +162,57 @@ __device__ bool slot_entry(const ModelDev& m, uint64_t a, uint64_t b, int s, uin
   return ok;
 }
 
-// One wave per row; lanes cover slots, valid entries compacted in slot order.
-__global__ void k_connected(ModelDev m, const uint64_t* __restrict__ cfg, int64_t B, int kmax,
+// One wave per row; lanes cover slots, valid entries compacted in slot order.  A wave takes
+// its rows 64 at a time: lane i loads the configuration of the i-th of them (one coalesced
+// load for 64 rows), each row reads its configuration from that lane, and the 64 counts are
+// stored together, so the only per-row memory operations are the entries' stores.
+__global__ void k_connected(ModelDev m_arg, const uint64_t* __restrict__ cfg, int64_t B, int kmax,
                             uint64_t* __restrict__ conn, float* __restrict__ mel,
                             int32_t* __restrict__ n_conn) {
+  const ModelDev m = in_regs(m_arg);
   const int lane = threadIdx.x & 63;
-  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t row = wave0; row < B; row += nwaves) {
-    const uint64_t a = cfg[2 * row], b = cfg[2 * row + 1];
-    int base = 0;
-    for (int s0 = 0; s0 < m.nslots; s0 += 64) {
-      const int s = s0 + lane;
-      uint64_t ya = 0, yb = 0;
-      float cre = 0.f, cim = 0.f;
-      const bool v = s < m.nslots && slot_entry(m, a, b, s, ya, yb, cre, cim);
-      const uint64_t bal = __ballot(v);
-      const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
-      if (v && pos < kmax) {
-        const int64_t o = row * kmax + pos;
-        conn[2 * o] = ya;
-        conn[2 * o + 1] = yb;
-        mel[2 * o] = cre;
-        mel[2 * o + 1] = cim;
+  const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t r0 = wave0; r0 < B; r0 += 64 * nwaves) {
+    const int64_t mine = r0 + lane * nwaves;
+    ulonglong2 cl = make_ulonglong2(0, 0);
+    if (mine < B) cl = reinterpret_cast<const ulonglong2*>(cfg)[mine];
+    wait_vmem();
+    const int nrows = (int)min<int64_t>(64, (B - r0 + nwaves - 1) / nwaves);
+    int count = 0;
+    for (int i = 0; i < nrows; ++i) {
+      const int64_t row = r0 + i * nwaves;
+      const uint64_t a = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(cl.x >> 32), i) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((uint32_t)cl.x, i);
+      const uint64_t b = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(cl.y >> 32), i) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((uint32_t)cl.y, i);
+      int base = 0;
+      for (int s0 = 0; s0 < m.nslots; s0 += 64) {
+        const int s = s0 + lane;
+        uint64_t ya = 0, yb = 0;
+        float cre = 0.f, cim = 0.f;
+        const bool v = s < m.nslots && slot_entry(m, a, b, s, ya, yb, cre, cim);
+        const uint64_t bal = __ballot(v);
+        const int pos = base + __popcll(bal & ((1ull << lane) - 1ull));
+        if (v && pos < kmax) {
+          const int64_t o = row * kmax + pos;
+          reinterpret_cast<ulonglong2*>(conn)[o] = make_ulonglong2(ya, yb);
+          reinterpret_cast<float2*>(mel)[o] = make_float2(cre, cim);
+        }
+        base += __popcll(bal);
       }
-      base += __popcll(bal);
+      count = lane == i ? base : count;
     }
-    if (lane == 0) n_conn[row] = base;
+    if (mine < B) n_conn[mine] = count;
   }
 }
 
 // Internal evaluation list: per row, entry 0 is x itself (coefficient = the
 // diagonal, possibly 0), followed by the valid off-diagonal entries in slot
 // order.  Pass 1 counts, pass 2 (after a scan) fills.
-__global__ void k_eval_count(ModelDev m, const uint64_t* __restrict__ cfg, int64_t B,
+__global__ void k_eval_count(ModelDev m_arg, const uint64_t* __restrict__ cfg, int64_t B,
                              int32_t* __restrict__ cnt) {
+  const ModelDev m = in_regs(m_arg);
   const int lane = threadIdx.x & 63;
   const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -186,9 +230,10 @@ __global__ void k_eval_count(ModelDev m, const uint64_t* __restrict__ cfg, int64
   }
 }
 
-__global__ void k_eval_fill(ModelDev m, const uint64_t* __restrict__ cfg, int64_t B,
+__global__ void k_eval_fill(ModelDev m_arg, const uint64_t* __restrict__ cfg, int64_t B,
                             const int64_t* __restrict__ off, uint64_t* __restrict__ ecfg,
                             float* __restrict__ ecoef, int32_t* __restrict__ eowner) {
+  const ModelDev m = in_regs(m_arg);
   const int lane = threadIdx.x & 63;
   const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -257,28 +302,58 @@ __device__ __forceinline__ float2 cexpf_diff(float2 y, float2 x) {
   return make_float2(er * cs, er * sn);
 }
 
-// L(x_b) = sum_k mel[b][k] exp(lr_conn[b][k] - lr_x[b]); one wave per row.
+// L(x_b) = sum_k mel[b][k] exp(lr_conn[b][k] - lr_x[b]); one wave per row.  A wave takes its
+// rows 64 at a time: lane i loads log rho(x) and the count of the i-th of them, each row reads
+// them from that lane, and the 64 results are stored together, so inside the row loop there
+// are only the entries' loads.  The next row's first 64 entries are loaded while the current
+// row is reduced; entries are loaded up to kmax regardless of the count (in bounds) and those
+// at or beyond the count are discarded by selection, so unwritten slots never enter the sum.
 __global__ void k_lloc_fixed(int64_t B, const float2* __restrict__ lrx, const float2* __restrict__ mel,
                              const int32_t* __restrict__ ncon, int kmax,
                              const float2* __restrict__ lrc, float2* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t row = wave0; row < B; row += nwaves) {
-    const float2 x = lrx[row];
-    const int k = ncon[row];
-    float re = 0.f, im = 0.f;
-    if (!(isinf(x.x) && x.x < 0.f)) {
-      for (int j = lane; j < k && j < kmax; j += 64) {
-        const float2 c = mel[row * kmax + j];
-        const float2 e = cexpf_diff(lrc[row * kmax + j], x);
-        re += c.x * e.x - c.y * e.y;
-        im += c.x * e.y + c.y * e.x;
+  const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t r0 = wave0; r0 < B; r0 += 64 * nwaves) {
+    const int64_t mine = r0 + lane * nwaves;
+    float2 xl = make_float2(0.f, 0.f);
+    int kl = 0;
+    if (mine < B) { xl = lrx[mine]; kl = min(ncon[mine], kmax); }
+    const int nrows = (int)min<int64_t>(64, (B - r0 + nwaves - 1) / nwaves);
+    float2 nc = make_float2(0.f, 0.f), nl = nc;
+    if (lane < kmax) { nc = mel[r0 * kmax + lane]; nl = lrc[r0 * kmax + lane]; }
+    wait_vmem();
+    float2 res = make_float2(0.f, 0.f);
+    for (int i = 0; i < nrows; ++i) {
+      const int64_t row = r0 + i * nwaves;
+      const float2 x = make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(xl.x), i)),
+                                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xl.y), i)));
+      const int k = __builtin_amdgcn_readlane(kl, i);
+      const float2 c0 = nc, l0 = nl;
+      const bool live = !(isinf(x.x) && x.x < 0.f);
+      float re = 0.f, im = 0.f;
+      if (live && lane < k) {
+        const float2 e = cexpf_diff(l0, x);
+        re = c0.x * e.x - c0.y * e.y;
+        im = c0.x * e.y + c0.y * e.x;
       }
+      if (live) {
+        for (int j = lane + 64; j < k; j += 64) {
+          const float2 c = mel[row * kmax + j];
+          const float2 e = cexpf_diff(lrc[row * kmax + j], x);
+          re += c.x * e.x - c.y * e.y;
+          im += c.x * e.y + c.y * e.x;
+        }
+      }
+      if (i + 1 < nrows && lane < kmax) {
+        nc = mel[(row + nwaves) * kmax + lane];
+        nl = lrc[(row + nwaves) * kmax + lane];
+      }
+      re = wave_sum(re);
+      im = wave_sum(im);
+      res = lane == i ? make_float2(re, im) : res;
     }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (lane == 0) out[row] = make_float2(re, im);
+    if (mine < B) out[mine] = res;
   }
 }
 
