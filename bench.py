@@ -99,7 +99,8 @@ def main():
     # evaluation-list, loss and reduction launches and a launch tail per kernel)
     ap.add_argument("--workspace-gib", type=float, default=128.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true", help="skip the loss check against the oracle")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the loss check against the oracle (it runs in the oracle leg, with the CPU baseline)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched-workload and sampler measurements (BF16, reported beside the headline)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -198,31 +199,27 @@ def main():
                     flops_per_unit=kernel_flops_per_unit(dom, n, d, m),
                     unit_def="one configuration-pass through one layer")
 
-    # matched loss error: the loss on sampled rows of the same batch, against the FP64 oracle
-    loss_err = None
-    if not args.no_check:
-        from oracle import ansatz as oa
-        from oracle import lindblad as ol
-        from oracle import vmc
-        pick = np.sort(np.random.default_rng(7).choice(B, 16, replace=False))
-        w = torch.zeros(B, dtype=torch.float64, device=dev)
-        w[torch.from_numpy(pick).to(dev)] = 1.0
-        F_ref, _, _ = vmc.loss(params_np.astype(np.float64), oa.Arch(**arch), ol.Model(**model), cfg_np[pick])
-        loss_err = {}
-        for prec in results:
-            lg, _, _ = ctx.loss_grad(arch, params, model, cfg, w, prec, "B")
-            loss_err[prec] = abs(float(lg[0]) - F_ref) / abs(F_ref)
-        log(f"bench: loss rel. error vs FP64 oracle on 16 sampled rows: {loss_err}")
-
     extras = None
     if not args.no_extras:
         extras = {"batched_uneven": bench_batched(ctx, tdo, synth, args.steps),
                   "sampler": bench_sampler(ctx, arch, params, n, synth),
                   "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
 
-    cpu = None
+    # the oracle leg (host): timed on a bounded sample, and (unless --no-check) the FP64 loss of
+    # 16 sampled rows of the same batch, against which the GPU losses on those rows are compared
+    cpu, F_ref = None, None
+    pick = np.sort(np.random.default_rng(7).choice(B, 16, replace=False))
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(arch, model, params_np, cfg_np)
+        cpu, F_ref = cpu_baseline(arch, model, params_np, cfg_np, None if args.no_check else pick)
+    loss_err = None
+    if F_ref is not None:
+        w = torch.zeros(B, dtype=torch.float64, device=dev)
+        w[torch.from_numpy(pick).to(dev)] = 1.0
+        loss_err = {}
+        for prec in results:
+            lg, _, _ = ctx.loss_grad(arch, params, model, cfg, w, prec, "B")
+            loss_err[prec] = abs(float(lg[0]) - F_ref) / abs(F_ref)
+        log(f"bench: loss rel. error vs FP64 oracle on 16 sampled rows: {loss_err}")
 
     out = {
         "metric": METRIC,
@@ -361,9 +358,11 @@ def bench_lindblad(ctx, tdo, model, synth, steps, B=1 << 20):
     return {"B": B, "n": n, "kmax": kmax, "entries": entries, "kernels": res}
 
 
-def cpu_baseline(arch, model, params_np, cfg_np):
-    """The FP64 oracle's loss and gradient (mode B) on a bounded prefix of the
-    same samples, timed on the host; scaled to configurations per second."""
+def cpu_baseline(arch, model, params_np, cfg_np, pick=None):
+    """The oracle leg: the FP64 oracle's loss and gradient (mode B) on a bounded
+    prefix of the same samples, timed on the host and scaled to configurations per
+    second; and, when pick is given, the oracle's loss on those rows (untimed).
+    Returns (baseline dict, loss on pick or None)."""
     import numpy as np
     import torch
 
@@ -385,8 +384,10 @@ def cpu_baseline(arch, model, params_np, cfg_np):
     S = int(min(max(2, round(2 * 15.0 / max(t, 1e-3))), 512))
     E, t = run(S)
     log(f"bench: oracle {S} samples ({E} configurations) in {t:.1f} s")
-    return {"value": E / t, "unit": "configs/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"first {S} of the 65536 samples ({E} configurations), FP64 loss and gradient (mode B)"}
+    F_ref = float(vmc.loss(th, A, M, cfg_np[pick])[0]) if pick is not None else None
+    return ({"value": E / t, "unit": "configs/s", "cores": torch.get_num_threads(), "kind": "oracle",
+             "sample": f"first {S} of the 65536 samples ({E} configurations), FP64 loss and gradient (mode B)"},
+            F_ref)
 
 
 if __name__ == "__main__":
