@@ -72,6 +72,17 @@ __device__ __forceinline__ void stage_ops(__bf16* m, int f0, const bf16x8& o0, c
   for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(m + soff(f0 + lr, 2 * s + h)) = cvt8(t, s);
 }
 
+// -l (a softmax normaliser negated) as three BF16 terms with hi + mid + lo = -l exactly
+// (each term the next 8 significant bits; -inf stays in hi), packed as two operand registers.
+__device__ __forceinline__ u32x2 neg_terms(float l) {
+  const float x = -l;
+  const float hi = (float)(__bf16)x;
+  const float r1 = __builtin_isinf(x) ? 0.f : x - hi;
+  const float mid = (float)(__bf16)r1;
+  const float lo = (float)(__bf16)(r1 - mid);
+  return (u32x2){pk2(hi, mid), pk2(lo, 0.f)};
+}
+
 }  // namespace
 
 template <int DH, bool MASKED>
@@ -243,7 +254,20 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     for (int j = 0; j < HPB; ++j) {
       const bool mine = (lr / DH) == j;
       // query-major tiles: lane -> query lr, values -> keys tile_idx(r, h)
-      f32x16 sq = PBF16::scores_packed<DH>(KRp[j], QRp[j], f32x16{});
+      f32x16 sq;
+      if constexpr (DH == 8) {
+        // S - lse on the matrix cores (one 16-deep product, the cost of the 8-deep one): the head's
+        // features at k = 8h + 0..3 of both operands, and in the first half's lanes the query's
+        // -lse as three exact BF16 terms against ones at k = 4..6
+        const u32x2 kb = __builtin_bit_cast(u32x2, KRp[j].v), qb = __builtin_bit_cast(u32x2, QRp[j].v);
+        const u32x2 t = neg_terms(lse[j]);
+        const uint32_t one2 = pk2(1.f, 1.f), one1 = pk2(1.f, 0.f);
+        const bf16x8 ko = __builtin_bit_cast(bf16x8, (u32x4){kb[0], kb[1], h == 0 ? one2 : 0u, h == 0 ? one1 : 0u});
+        const bf16x8 qo = __builtin_bit_cast(bf16x8, (u32x4){qb[0], qb[1], h == 0 ? t[0] : 0u, h == 0 ? t[1] : 0u});
+        sq = mfma16(ko, qo, f32x16{});
+      } else {
+        sq = PBF16::scores_packed<DH>(KRp[j], QRp[j], f32x16{});
+      }
       f32x16 dpq = PBF16::scores_packed<DH>(VRp[j], ORp[j], f32x16{});
       if constexpr (MASKED) {  // a compile-time choice keeps the head loop one scheduling region
 #pragma unroll
@@ -255,7 +279,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       float dl = 0.f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        sq[r] = __builtin_amdgcn_exp2f(sq[r] - lse[j]);  // P
+        sq[r] = __builtin_amdgcn_exp2f(DH == 8 ? sq[r] : sq[r] - lse[j]);  // P
         dl += sq[r] * dpq[r];
       }
       dl = xor32_sum(dl);
