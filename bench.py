@@ -107,6 +107,9 @@ def main():
                     help="also run one elementwise copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--lindblad-only", action="store_true",
                     help="measure only tdo_connected and tdo_local_lindbladian (HBM-bound) and print their line")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="measure only the batched workload (64 uneven problems) and print its line")
+    ap.add_argument("--sampler-only", action="store_true", help="measure only the sampler and print its line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the samples shard "
@@ -149,9 +152,15 @@ def main():
         log(f"bench: calibration copy of {args.copy_calibration_mib} MiB done")
         del src, dst
 
-    if args.lindblad_only:
-        print(json.dumps({"metric": "Lindbladian rows and L_loc, algorithmic HBM GB/s",
-                          "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}), flush=True)
+    if args.lindblad_only or args.batched_only or args.sampler_only:
+        if args.lindblad_only:
+            line = {"metric": "Lindbladian rows and L_loc, algorithmic HBM GB/s",
+                    "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
+        elif args.batched_only:
+            line = {"metric": "batched workload, configs/s", "batched_uneven": bench_batched(ctx, tdo, synth, args.steps)}
+        else:
+            line = {"metric": "Metropolis sampler, proposals/s", "sampler": bench_sampler(ctx, arch, params, n, synth)}
+        print(json.dumps(line), flush=True)
         ctx.close()
         return
 
