@@ -210,7 +210,9 @@ def main():
 
     extras = None
     if not args.no_extras:
-        extras = {"batched_uneven": bench_batched(ctx, tdo, synth, args.steps),
+        extras = {"ising_n8": bench_small(ctx, tdo, synth, "ising_n8", args.steps),
+                  "xyz_n16": bench_small(ctx, tdo, synth, "xyz_n16", args.steps),
+                  "batched_uneven": bench_batched(ctx, tdo, synth, args.steps),
                   "sampler": bench_sampler(ctx, arch, params, n, synth),
                   "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
 
@@ -265,6 +267,58 @@ def evaluated_configs(ctx, model, cfg):
     conn, _, ncon = ctx.connected(model, cfg)
     diag = (conn[:, 0, 0] == cfg[:, 0]) & (conn[:, 0, 1] == cfg[:, 1])
     return int(ncon.sum().item()) + int((~diag).sum().item())
+
+
+def bench_small(ctx, tdo, synth, name, steps):
+    """A smaller workload (Ising n = 8 at width 32, B = 4096; XYZ n = 16 at width 64 with
+    4 heads, B = 16384), FP32 and BF16: configurations per second of tdo_loss_grad (mode
+    B, forward and backward) and of tdo_log_rho alone over the same evaluated
+    configurations (each sample and its nonzero off-diagonal entries, gathered before
+    timing), with the BF16 speed-ups."""
+    import torch
+    wl = synth.workload(name)
+    arch, model, B = wl["arch"], wl["model"], wl["B"]
+    params = torch.from_numpy(synth.params(arch, wl["seed"], "init")).cuda()
+    cfg = torch.from_numpy(synth.configs(model["n"], B, 3000)).cuda()
+    E = evaluated_configs(ctx, model, cfg)
+    conn, _, ncon = ctx.connected(model, cfg)
+    kmax = conn.shape[1]
+    valid = torch.arange(kmax, device=cfg.device)[None, :] < ncon[:, None].long()
+    ci, xi = conn.view(torch.int64), cfg.view(torch.int64)  # (index and compare as int64 bit patterns)
+    offd = valid & ~((ci[:, :, 0] == xi[:, None, 0]) & (ci[:, :, 1] == xi[:, None, 1]))
+    evalset = torch.cat([xi, ci[offd]], 0).contiguous().view(torch.uint64)
+    del conn
+    assert evalset.shape[0] == E
+    res = {"n": model["n"], "arch": arch, "B": B, "configs_per_step": E}
+    for prec in ("fp32", "bf16"):
+        ctx.log_rho(arch, params, model["n"], evalset, prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(8):
+            ctx.log_rho(arch, params, model["n"], evalset, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        res["forward_" + prec] = {"ms": e0.elapsed_time(e1) / 8, "configs_per_s": E / (e0.elapsed_time(e1) / 8 / 1e3)}
+    res["forward_speedup_bf16_over_fp32"] = res["forward_bf16"]["configs_per_s"] / res["forward_fp32"]["configs_per_s"]
+    for prec in ("fp32", "bf16"):
+        ctx.loss_grad(arch, params, model, cfg, None, prec, "B")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 4 * max(steps, 1)
+        e0.record()
+        for _ in range(reps):
+            ctx.loss_grad(arch, params, model, cfg, None, prec, "B")
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[prec] = {"ms_per_step": ms, "configs_per_s": E / (ms / 1e3)}
+    res["speedup_bf16_over_fp32"] = res["bf16"]["configs_per_s"] / res["fp32"]["configs_per_s"]
+    log(f"bench: {name} B={B} ({E} configurations): loss+gradient fp32 {res['fp32']['configs_per_s'] / 1e6:.3f} M/s, "
+        f"bf16 {res['bf16']['configs_per_s'] / 1e6:.3f} M/s ({res['speedup_bf16_over_fp32']:.1f}x); forward fp32 "
+        f"{res['forward_fp32']['configs_per_s'] / 1e6:.2f} M/s, bf16 {res['forward_bf16']['configs_per_s'] / 1e6:.2f} M/s "
+        f"({res['forward_speedup_bf16_over_fp32']:.1f}x)")
+    return res
 
 
 def bench_batched(ctx, tdo, synth, steps):
