@@ -191,16 +191,26 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       else stage_ops(S + SG * MAT, 32 * ib, go[ib][0], go[ib][1], eye, lr, h);
     }
 
-    // projections of the 32 attention features of head block hb, both orientations
-    // (*R: lane -> row, values -> features; *F: lane -> feature, values -> rows),
-    // formed in two groups and packed to BF16 operands right away to keep the
-    // register peak low: per-head score operands (q scaled by log2(e)/sqrt(dh)),
-    // and the feature-major tiles, masked per head below
+    // projections of the 32 attention features of head block hb, row-major (*R: lane -> row,
+    // values -> features), packed to BF16 operands right away to keep the register peak low:
+    // per-head score operands (q scaled by log2(e)/sqrt(dh), dO by 1/sqrt(dh)).  The
+    // feature-major tiles (*F: lane -> feature, values -> rows; masked per head below) are
+    // exact MFMA transposes of those BF16 operands, half the MFMAs of projecting again; dK
+    // and dV, formed from the scaled q and dO, are rescaled after the head loop.
     using sop = PBF16::SOp<DH>;
     sop QRp[HPB], KRp[HPB], VRp[HPB], ORp[HPB];
     bf16x8 QFb[ST], KFb[ST], VFb[ST], OFb[ST];
+    // row-major operand s (values 8s .. 8s+7) of a projection from its per-head packs
+    auto rop = [&](const sop (&P)[HPB], int s) -> bf16x8 {
+      if constexpr (DH == 8) {
+        const u32x2 lo = __builtin_bit_cast(u32x2, P[2 * s].v), hi = __builtin_bit_cast(u32x2, P[2 * s + 1].v);
+        return __builtin_bit_cast(bf16x8, (u32x4){lo[0], lo[1], hi[0], hi[1]});
+      } else {
+        return P[s].v;
+      }
+    };
     {
-      f32x16 QR = {}, KR = {}, QF = {}, KF = {};
+      f32x16 QR = {}, KR = {};
 #pragma unroll
       for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
@@ -208,9 +218,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
           const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
           const bf16x8 wq = ld8(Wq + f * 8), wk = ld8(Wk + f * 8);
           QR = mfma16(wq, xo[ib][s], QR);
-          QF = mfma16(xo[ib][s], wq, QF);
           KR = mfma16(wk, xo[ib][s], KR);
-          KF = mfma16(xo[ib][s], wk, KF);
         }
 #pragma unroll
       for (int r = 0; r < 16; ++r) QR[r] *= sc;
@@ -219,11 +227,13 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         QRp[j] = PBF16::pack_head<DH>(QR, j);
         KRp[j] = PBF16::pack_head<DH>(KR, j);
       }
+      const f32x16 QF = transpose_mfma(rop(QRp, 0), rop(QRp, 1), eye);
+      const f32x16 KF = transpose_mfma(rop(KRp, 0), rop(KRp, 1), eye);
 #pragma unroll
       for (int s = 0; s < ST; ++s) { QFb[s] = cvt8(QF, s); KFb[s] = cvt8(KF, s); }
     }
     {
-      f32x16 VR = {}, OR = {}, VF = {}, OF = {};  // V and dO = g W_O^T
+      f32x16 VR = {}, OR = {};  // V and dO = g W_O^T
 #pragma unroll
       for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
@@ -231,9 +241,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
           const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
           const bf16x8 wv = ld8(Wv + f * 8), wo = ld8(WoT + f * 8);
           VR = mfma16(wv, xo[ib][s], VR);
-          VF = mfma16(xo[ib][s], wv, VF);
           OR = mfma16(wo, go[ib][s], OR);
-          OF = mfma16(go[ib][s], wo, OF);
         }
       // dO as the score operand of dP carries the factor 1/sqrt(dh) of dS
 #pragma unroll
@@ -243,6 +251,8 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         VRp[j] = PBF16::pack_head<DH>(VR, j);
         ORp[j] = PBF16::pack_head<DH>(OR, j);
       }
+      const f32x16 VF = transpose_mfma(rop(VRp, 0), rop(VRp, 1), eye);
+      const f32x16 OF = transpose_mfma(rop(ORp, 0), rop(ORp, 1), eye);
 #pragma unroll
       for (int s = 0; s < ST; ++s) { VFb[s] = cvt8(VF, s); OFb[s] = cvt8(OF, s); }
     }
@@ -306,6 +316,12 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       }
     }
     // stage dQ, dK, dV (R layout -> [feature][row]) and O (F layout: two 16-byte writes per lane)
+    // dK and dV were formed from q scaled by sc and dO scaled by 1/sqrt(dh)
+    {
+      const float isc = 1.0f / sc, sdh = 1.0f / isd;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { dKR[r] *= isc; dVR[r] *= sdh; }
+    }
     bf16x8 dq[ST], dk[ST], dv[ST];
 #pragma unroll
     for (int s = 0; s < ST; ++s) { dq[s] = cvt8(dQR, s); dk[s] = cvt8(dKR, s); dv[s] = cvt8(dVR, s); }
