@@ -514,14 +514,23 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
         else stage_ops(S + SG * MAT, 32 * ib, go[rb][ib][0], go[rb][ib][1], eye, lr, h);
       }
     }
-    // projections of head block hb for both blocks (see the kernel above)
+    // projections of head block hb for both blocks (see the kernel above: the feature-major
+    // tiles are MFMA transposes of the row-major BF16 operands; dK, dV rescaled below)
     using sop = PBF16::SOp<DH>;
     sop QRp[2][HPB], KRp[2][HPB], VRp[2][HPB], ORp[2][HPB];
     bf16x8 QFb[2][ST], KFb[2][ST], VFb[2][ST], OFb[2][ST];
+    auto rop = [&](const sop (&P)[HPB], int s) -> bf16x8 {
+      if constexpr (DH == 8) {
+        const u32x2 lo = __builtin_bit_cast(u32x2, P[2 * s].v), hi = __builtin_bit_cast(u32x2, P[2 * s + 1].v);
+        return __builtin_bit_cast(bf16x8, (u32x4){lo[0], lo[1], hi[0], hi[1]});
+      } else {
+        return P[s].v;
+      }
+    };
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
       {
-        f32x16 QR = {}, KR = {}, QF = {}, KF = {};
+        f32x16 QR = {}, KR = {};
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
@@ -529,9 +538,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
             const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
             const bf16x8 wq = ld8(Wq + f * 8), wk = ld8(Wk + f * 8);
             QR = mfma16(wq, xo[rb][ib][s], QR);
-            QF = mfma16(xo[rb][ib][s], wq, QF);
             KR = mfma16(wk, xo[rb][ib][s], KR);
-            KF = mfma16(xo[rb][ib][s], wk, KF);
           }
 #pragma unroll
         for (int r = 0; r < 16; ++r) QR[r] *= sc;
@@ -540,11 +547,13 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           QRp[rb][j] = PBF16::pack_head<DH>(QR, j);
           KRp[rb][j] = PBF16::pack_head<DH>(KR, j);
         }
+        const f32x16 QF = transpose_mfma(rop(QRp[rb], 0), rop(QRp[rb], 1), eye);
+        const f32x16 KF = transpose_mfma(rop(KRp[rb], 0), rop(KRp[rb], 1), eye);
 #pragma unroll
         for (int s = 0; s < ST; ++s) { QFb[rb][s] = cvt8(QF, s); KFb[rb][s] = cvt8(KF, s); }
       }
       {
-        f32x16 VR = {}, OR = {}, VF = {}, OF = {};
+        f32x16 VR = {}, OR = {};
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
@@ -552,9 +561,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
             const int f = ((hb * NB + ib) * ST + s) * 64 + lane;
             const bf16x8 wv = ld8(Wv + f * 8), wo = ld8(WoT + f * 8);
             VR = mfma16(wv, xo[rb][ib][s], VR);
-            VF = mfma16(xo[rb][ib][s], wv, VF);
             OR = mfma16(wo, go[rb][ib][s], OR);
-            OF = mfma16(go[rb][ib][s], wo, OF);
           }
         // dO as the score operand of dP carries the factor 1/sqrt(dh) of dS
 #pragma unroll
@@ -564,6 +571,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           VRp[rb][j] = PBF16::pack_head<DH>(VR, j);
           ORp[rb][j] = PBF16::pack_head<DH>(OR, j);
         }
+        const f32x16 VF = transpose_mfma(rop(VRp[rb], 0), rop(VRp[rb], 1), eye);
+        const f32x16 OF = transpose_mfma(rop(ORp[rb], 0), rop(ORp[rb], 1), eye);
 #pragma unroll
         for (int s = 0; s < ST; ++s) { VFb[rb][s] = cvt8(VF, s); OFb[rb][s] = cvt8(OF, s); }
       }
@@ -618,9 +627,12 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
       }
     }
     bf16x8 dq[2][ST], dk[2][ST], dv[2][ST];
+    const float isc = 1.0f / sc, sdh = 1.0f / isd;  // dK, dV were formed from the scaled q and dO
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
       __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) { dKR[rb][r] *= isc; dVR[rb][r] *= sdh; }
 #pragma unroll
       for (int s = 0; s < ST; ++s) { dq[rb][s] = cvt8(dQR[rb], s); dk[rb][s] = cvt8(dKR[rb], s); dv[rb][s] = cvt8(dVR[rb], s); }
       stage_ops(S + SQ * MAT, 32 * hb, dq[rb][0], dq[rb][1], eye, lr, h);
