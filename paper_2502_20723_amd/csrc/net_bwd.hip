@@ -430,8 +430,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn(BwdArgs a) {
 // dW_head[f][k] += sum over configuration-passes of (mean over its rows of x_L[f]) dF_k,
 // db_head[k] += dF_k.  One wave per block of the saved x_L (lane -> row, values ->
 // features): each lane adds x_L[row][f] dF_k / n for its row into FP64
-// accumulators; the lanes of a feature are summed once per launch and added to
-// the FP64 gradient atomically.
+// accumulators; once per launch the lanes and the waves of a workgroup are summed in a
+// fixed order into the workgroup's slot, and k_reduce_head adds the slots to the gradient.
 template <class P, int D>
 __global__ void __launch_bounds__(256) k_bwd_head(const void* __restrict__ save_last, const float* __restrict__ seeds,
                                                   const int64_t* E_dev, int64_t E_host, int n, int cpb, int span,

@@ -13,17 +13,16 @@
 // (attention features [32 (w/4), 32 (w/4) + 32)) of block w % 4 of the tile,
 // then owns rows [32 (w/4), 32 (w/4) + 32) of one weight gradient (w % 4 = 0..3:
 // Wq, Wk, Wv, W_O) accumulated in registers for the whole launch.  The two waves
-// of a block add their dx terms in turn through the output buffer: head block 0
-// writes g + its terms before the workgroup barrier, head block 1 adds its terms
-// after it, the order of a single wave walking both head blocks.
+// of a block add their dx terms in turn through LDS: head block 0 leaves g + its
+// terms in the exchange area before the workgroup barrier, head block 1 adds its
+// terms after it and writes dx.
 //
 // Block phase (one wave per head block).  Every contraction over keys or queries needs its
 // operands with lanes enumerating features and values enumerating rows, the
-// transpose of what the projections give.  The projections are therefore
-// formed in both orientations (the same weight fragments serve as A or B
-// operand), and the per-head probability and dS tiles, computed query-major,
-// are transposed to key-major on the matrix cores (transpose_mfma: an exact
-// product with a 0/1 permutation operand), as are the tiles staged below.
+// transpose of what the projections give.  Those feature-major tiles, the
+// key-major probability and dS tiles (computed query-major) and the tiles
+// staged below are all transposed on the matrix cores (transpose_mfma: an exact
+// product with a 0/1 permutation operand).
 //
 // Gradient phase (all waves).  x, g, O, dQ, dK, dV of each block are staged
 // in LDS as [feature][row] BF16 with the rows of each 16-row group in the
