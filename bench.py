@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="measure only the batched workload (64 uneven problems) and print its line")
     ap.add_argument("--sampler-only", action="store_true", help="measure only the sampler and print its line")
+    ap.add_argument("--observables-only", action="store_true",
+                    help="measure only the observables, purity and diagonal sampler and print their line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the samples shard "
@@ -152,8 +154,11 @@ def main():
         log(f"bench: calibration copy of {args.copy_calibration_mib} MiB done")
         del src, dst
 
-    if args.lindblad_only or args.batched_only or args.sampler_only:
-        if args.lindblad_only:
+    if args.lindblad_only or args.batched_only or args.sampler_only or args.observables_only:
+        if args.observables_only:
+            line = {"metric": "mixed-state observables, samples/s",
+                    "observables": bench_observables(ctx, arch, params, n, synth)}
+        elif args.lindblad_only:
             line = {"metric": "Lindbladian rows and L_loc, algorithmic HBM GB/s",
                     "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
         elif args.batched_only:
@@ -214,6 +219,7 @@ def main():
                   "xyz_n16": bench_small(ctx, tdo, synth, "xyz_n16", args.steps),
                   "batched_uneven": bench_batched(ctx, tdo, synth, args.steps),
                   "sampler": bench_sampler(ctx, arch, params, n, synth),
+                  "observables": bench_observables(ctx, arch, params, n, synth),
                   "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
 
     # the oracle leg (host): timed on a bounded sample, and (unless --no-check) the FP64 loss of
@@ -372,6 +378,54 @@ def bench_sampler(ctx, arch, params, n, synth):
     props = C * 2 * n
     log(f"bench: sampler {C} chains x {2 * n} proposals in {ms:.1f} ms: {props / ms * 1e3 / 1e6:.2f} M proposals/s")
     return {"value": props / (ms / 1e3), "unit": "proposals/s", "chains": C, "sweeps": 1, "ms": ms, "dtype": "bf16"}
+
+
+def bench_observables(ctx, arch, params, n, synth):
+    """Mixed-state observables with the n = 32 network, BF16: local estimators of
+    the three magnetisation components and their sign-weighted means over 65536
+    samples (n + 1 = 33 network rows each), the purity over 32768 pairs (3 rows
+    each), and the diagonal chain (65536 chains, one sweep of n proposals).  Each
+    is timed with HIP events after one untimed call.  FLOP/s counts the forward
+    layers' algorithmic FLOPs (two configuration-passes per row)."""
+    import numpy as np
+    import torch
+    B, Pp, C = 65536, 32768, 65536
+    d, m, L = arch["d"], arch["mlp"], arch["layers"]
+    row_flops = 2 * L * (8 * n * d * d + 4 * n * n * d + 4 * n * d * m)
+    alpha = torch.from_numpy(np.ascontiguousarray(synth.configs(n, B, 6000)[:, 0])).cuda()
+    pairs = torch.from_numpy(synth.configs(n, Pp, 6001)).cuda()
+    pa, pb = pairs[:, 0].contiguous(), pairs[:, 1].contiguous()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    out = {}
+    ms = timed(lambda: ctx.observables(arch, params, n, alpha, "bf16"))
+    rows = B * (n + 1)
+    out["local_estimators"] = {"value": B / (ms / 1e3), "unit": "samples/s", "samples": B, "rows": rows, "ms": ms,
+                               "tflops": rows * row_flops / (ms / 1e3) / 1e12, "dtype": "bf16"}
+    ms = timed(lambda: ctx.purity(arch, params, n, pa, pb, "bf16"))
+    out["purity"] = {"value": Pp / (ms / 1e3), "unit": "pairs/s", "pairs": Pp, "rows": 3 * Pp, "ms": ms,
+                     "tflops": 3 * Pp * row_flops / (ms / 1e3) / 1e12, "dtype": "bf16"}
+    state = alpha.clone()
+    slr = ctx.log_rho(arch, params, n, torch.stack([state, state], 1).contiguous(), "bf16")
+    ctr = [0]
+
+    def chain():
+        _, ctr[0] = ctx.sample_diag(arch, params, n, state, slr, 3, ctr[0], 1, "bf16")
+
+    ms = timed(chain)
+    out["diag_sampler"] = {"value": C * n / (ms / 1e3), "unit": "proposals/s", "chains": C, "sweeps": 1, "ms": ms,
+                           "dtype": "bf16"}
+    log("bench: observables " + ", ".join(f"{k} {v['value'] / 1e6:.2f} M {v['unit']}" for k, v in out.items()))
+    return out
 
 
 def bench_lindblad(ctx, tdo, model, synth, steps, B=1 << 20):

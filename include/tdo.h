@@ -195,6 +195,59 @@ int32_t tdo_sample(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, 
                    uint64_t *counter, int32_t sweeps, float p_pair, tdo_prec_t prec,
                    uint64_t *samples, hipStream_t stream);
 
+/* Metropolis-Hastings on the diagonal, P(alpha) ~ |rho(alpha, alpha)|: the
+ * distribution of the mixed-state observable estimators (supplementary section
+ * on mixed-state observables; App. C, sampling strategy).  The ansatz's
+ * diagonal is real but may be negative, so the chain targets its modulus and
+ * the sign is applied as a weight by tdo_observables and tdo_purity.
+ * `chains` independent chains, `sweeps` sweeps of n proposals each.  Proposal t
+ * of chain c draws Philox4x32-10 with counter (t mod 2^32, t >> 32, c, 1) and
+ * key (seed mod 2^32, seed >> 32), words r1, r2: flip site i = (r1 n) >> 32 of
+ * alpha; accept iff (r2 + 0.5) 2^-32 < exp(Re log rho(alpha', alpha') -
+ * Re log rho(alpha, alpha)).
+ * state: device uint64 [chains] in/out (alpha); state_log_rho: device float
+ * [chains][2] in/out, log rho(alpha, alpha) of the states (tdo_log_rho of the
+ * rows (alpha, alpha)); counter: host uint64 in/out, the proposal index of the
+ * first proposal (advanced by sweeps*n); samples: device uint64
+ * [sweeps][chains], alpha after each sweep.  A chain whose state has
+ * rho(alpha, alpha) = 0 accepts the first proposal with a nonzero diagonal. */
+int32_t tdo_sample_diag(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                        int64_t chains, uint64_t *state, float *state_log_rho, uint64_t seed,
+                        uint64_t *counter, int32_t sweeps, tdo_prec_t prec, uint64_t *samples,
+                        hipStream_t stream);
+
+/* Local estimators of the magnetisation (supplementary section on mixed-state
+ * observables; App. C, evaluation of local observables; Heisenberg section for
+ * the site averages): for each sample alpha (device uint64 [B]),
+ *   A~(alpha) = sum_beta rho(alpha, beta) / rho(alpha, alpha) <beta|A|alpha>
+ * for A = (1/n) sum_i sigma^k_i, k = x, y, z, with bit 0 = spin up
+ * (sigma^z = +1).  One sample costs n + 1 network evaluations, the rows
+ * (alpha, alpha) and (alpha, alpha with site i flipped).
+ * log_rho_diag: device float [B][2], log rho(alpha, alpha) (imaginary part pi
+ * where the diagonal is negative, real part -inf where it vanishes);
+ * local: device float [B][3][2], (re, im) of A~ for x, y, z.  Where
+ * rho(alpha, alpha) = 0 the ratios are read as 0 (sigma^z keeps its diagonal
+ * value).  mean: device double [7] or NULL: mean[0..5] = sum s A~ / sum s over
+ * the B samples for x, y, z as (re, im), with s = sign of rho(alpha, alpha),
+ * the estimate of <A> when the samples come from |rho(alpha, alpha)|
+ * (tdo_sample_diag); mean[6] = sum s / B.  mean needs B >= 1; sum s = 0 gives
+ * non-finite means.  Sums are FP64 in a fixed order. */
+int32_t tdo_observables(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                        const uint64_t *alpha, int64_t B, tdo_prec_t prec, float *log_rho_diag,
+                        float *local, double *mean, hipStream_t stream);
+
+/* Purity Tr(rho^2) / (Tr rho)^2 (Ising section) from P >= 1 pairs of
+ * independent diagonal samples (alpha_p, beta_p) (device uint64 [P] each, e.g.
+ * two different chains of tdo_sample_diag):
+ *   out[0] = mean_p t_p / (mean s)^2,
+ *   t_p = |rho(alpha, beta)|^2 / (|rho(alpha, alpha)| |rho(beta, beta)|),
+ * with s the sign of the diagonal over all 2P samples; out[1] = mean s.
+ * t_p = 0 when either diagonal vanishes.  Three network evaluations per pair.
+ * out: device double [2].  Sums are FP64 in a fixed order. */
+int32_t tdo_purity(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                   const uint64_t *alpha, const uint64_t *beta, int64_t P, tdo_prec_t prec,
+                   double *out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

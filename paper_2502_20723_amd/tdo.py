@@ -21,7 +21,8 @@ PREC = {"fp32": TDO_FP32, "bf16": TDO_BF16}
 # The entry points declared in include/tdo.h.
 EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_error", "tdo_profile",
            "tdo_profile_read", "tdo_connected", "tdo_local_lindbladian", "tdo_log_rho", "tdo_log_rho_vjp",
-           "tdo_loss_grad", "tdo_loss_grad_batched", "tdo_sample")
+           "tdo_loss_grad", "tdo_loss_grad_batched", "tdo_sample", "tdo_sample_diag", "tdo_observables",
+           "tdo_purity")
 
 
 class ArchT(ctypes.Structure):
@@ -67,6 +68,10 @@ def lib() -> ctypes.CDLL:
                                             i32, vp, vp, vp]
         L.tdo_sample.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, i64, vp, vp, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_uint64), i32, ctypes.c_float, i32, vp, vp]
+        L.tdo_sample_diag.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, i64, vp, vp, ctypes.c_uint64,
+                                      ctypes.POINTER(ctypes.c_uint64), i32, i32, vp, vp]
+        L.tdo_observables.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp, vp, vp]
+        L.tdo_purity.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, vp, i64, i32, vp, vp]
         for name in EXPORTS:
             if name not in ("tdo_last_error", "tdo_num_params", "tdo_ctx_create", "tdo_ctx_destroy"):
                 getattr(L, name).restype = i32
@@ -251,6 +256,43 @@ class Ctx:
         _check(lib().tdo_sample(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, C, _ptr(state), _ptr(state_lr),
                                 seed, ctypes.byref(ctr), sweeps, p_pair, PREC[prec], _ptr(samples), _stream()))
         return samples, int(ctr.value)
+
+    def sample_diag(self, arch: dict, params, n: int, state, state_lr, seed: int, counter: int, sweeps: int,
+                    prec="fp32"):
+        C = state.shape[0]
+        _dev(params, torch.float32, (num_params(arch),), "params")
+        _dev(state, torch.uint64, (C,), "state")
+        _dev(state_lr, torch.float32, (C, 2), "state_log_rho")
+        samples = torch.empty((sweeps, C), dtype=torch.uint64, device=state.device)
+        ctr = ctypes.c_uint64(counter)
+        _check(lib().tdo_sample_diag(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, C, _ptr(state),
+                                     _ptr(state_lr), seed, ctypes.byref(ctr), sweeps, PREC[prec], _ptr(samples),
+                                     _stream()))
+        return samples, int(ctr.value)
+
+    def observables(self, arch: dict, params, n: int, alpha, prec="fp32", want_mean=True):
+        """(log rho(alpha, alpha) [B, 2], local estimators [B, 3, 2] (x, y, z site averages),
+        sign-weighted means [7] float64 or None)."""
+        B = alpha.shape[0]
+        _dev(params, torch.float32, (num_params(arch),), "params")
+        _dev(alpha, torch.uint64, (B,), "alpha")
+        lrd = torch.empty((B, 2), dtype=torch.float32, device=alpha.device)
+        local = torch.empty((B, 3, 2), dtype=torch.float32, device=alpha.device)
+        mean = torch.empty((7,), dtype=torch.float64, device=alpha.device) if want_mean else None
+        _check(lib().tdo_observables(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(alpha), B,
+                                     PREC[prec], _ptr(lrd), _ptr(local), _ptr(mean), _stream()))
+        return lrd, local, mean
+
+    def purity(self, arch: dict, params, n: int, alpha, beta, prec="fp32"):
+        """[purity estimate, mean sign] (float64, device) from pairs (alpha_p, beta_p)."""
+        P = alpha.shape[0]
+        _dev(params, torch.float32, (num_params(arch),), "params")
+        _dev(alpha, torch.uint64, (P,), "alpha")
+        _dev(beta, torch.uint64, (P,), "beta")
+        out = torch.empty((2,), dtype=torch.float64, device=alpha.device)
+        _check(lib().tdo_purity(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(alpha), _ptr(beta), P,
+                                PREC[prec], _ptr(out), _stream()))
+        return out
 
 
 _default_ctx = None

@@ -1,0 +1,331 @@
+"""GPU parity of the mixed-state observables (tdo_observables), the purity
+(tdo_purity) and the diagonal Metropolis chain (tdo_sample_diag) through the
+C-ABI, against the FP64 oracle (oracle.observables).
+
+Local estimators are ratios r = rho(alpha, beta)/rho(alpha, alpha) = exp(dlog rho):
+their error is |r| times the errors of the two log rho values.  log rho =
+log(e^z1 + conj e^z2) loses relative accuracy where the two terms cancel: an
+error e in z becomes e k in log rho, k = (|e^z1| + |e^z2|) / |e^z1 + conj e^z2|
+(k = 1/|cos Im z| on the diagonal).  The bound on a sample is therefore
+TOL (1 + mean_i |r_i| (k_i + k_d)), with k from the oracle's z; sigma^z is
+exact.  Tolerances (stated): FP32 2e-4, BF16 8e-2 (BF16 log rho carries up to
+2e-2 away from cancellation)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy import stats
+
+from oracle import ansatz as oa
+from oracle import observables as ob
+from paper_2502_20723_amd import synth
+from tests.bf16_emulation import log_rho_emulated
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 2e-4, "bf16": 8e-2}
+SMALL = dict(d=16, heads=2, layers=1, mlp=64)
+MARGIN = 1e-3
+
+
+def cuda(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def alphas(n, B, seed):
+    return np.ascontiguousarray(synth.configs(n, B, seed)[:, 0])
+
+
+def cancellation(params, arch, n, cfg):
+    """k = (|e^z1| + |e^z2|) / |e^z1 + conj e^z2| of each row, from the oracle's z."""
+    th = torch.as_tensor(params.astype(np.float64))
+    A = oa.Arch(**arch)
+    x, y = oa.unpack_bits(cfg, n)
+    with torch.no_grad():
+        z1, z2 = oa.z_out(th, A, x, y).numpy(), oa.z_out(th, A, y, x).numpy()
+    m = np.maximum(z1.real, z2.real)
+    e1, e2 = np.exp(z1 - m), np.exp(np.conj(z2) - m)
+    return (np.abs(e1) + np.abs(e2)) / np.maximum(np.abs(e1 + e2), 1e-300)
+
+
+def oracle_local(params, arch, n, a):
+    """Oracle estimators [S, n, 3], log rho(a, a) [S], and the cancellation
+    factors of the diagonal row [S] and of the flipped rows [S, n]."""
+    f = ob.ansatz_log_rho(params.astype(np.float64), oa.Arch(**arch), n)
+    est = ob.local_estimators(f, a, n)
+    lr = f(np.stack([a, a], axis=1))
+    kd = cancellation(params, arch, n, np.stack([a, a], axis=1))
+    flips = np.stack([np.stack([a, a ^ (np.uint64(1) << np.uint64(i))], axis=1) for i in range(n)], axis=1)
+    ko = cancellation(params, arch, n, flips.reshape(-1, 2)).reshape(len(a), n)
+    return est, lr, kd, ko
+
+
+def check_local(local, lrd, ref, prec, what):
+    est, lr, kd, ko = ref
+    avg = est.mean(axis=1)                                  # [S, 3]
+    got = local[:, :, 0] + 1j * local[:, :, 1]
+    scale = 1.0 + (np.abs(est[:, :, 0]) * (ko + kd[:, None])).mean(axis=1)
+    err = np.abs(got - avg) / scale[:, None]
+    derr = np.abs(lrd[:, 0] - lr.real) / kd
+    print(f"{what} {prec}: local estimator max err {err[:, :2].max():.3e} (scaled), "
+          f"log rho(a,a) max err {derr.max():.3e} (scaled), max k {max(kd.max(), ko.max()):.1f}")
+    assert err[:, :2].max() < TOL[prec]
+    assert np.array_equal(local[:, 2, 0], avg[:, 2].real.astype(np.float32))   # sigma^z exact
+    assert np.all(local[:, 2, 1] == 0)
+    assert derr.max() < TOL[prec]
+    sure = kd * TOL[prec] < 0.5                             # sign not within the error of the diagonal
+    neg = np.abs(lr.imag) > 1.0
+    assert np.array_equal((np.abs(lrd[:, 1]) > 1.0)[sure], neg[sure])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name,n,B", [("ising_n8", 8, 700), ("xyz_n16", 16, 333), ("ising_n8", 5, 97)])
+def test_local_estimators_and_mean(gpu, prec, name, n, B):
+    """Several forward tiles and a ragged tail; stress weights give O(1) ratios
+    and some negative diagonals."""
+    arch = synth.WORKLOADS[name]["arch"]
+    params = synth.params(arch, 40 + n, "stress")
+    a = alphas(n, B, 41 + n)
+    ctx = gpu.Ctx(0)
+    lrd, local, mean = ctx.observables(arch, cuda(params), n, cuda(a), prec)
+    lrd, local, mean = lrd.cpu().numpy(), local.cpu().numpy(), mean.cpu().numpy()
+    ref = oracle_local(params, arch, n, a)
+    check_local(local, lrd, ref, prec, f"{name} n={n} B={B}")
+    est, lr, kd, ko = ref
+    want, msign = ob.sampled_expectation(lr, est)
+    got = mean[0:6:2] + 1j * mean[1:6:2]
+    flips = np.sum(((np.abs(lrd[:, 1]) > 1.0) != (np.abs(lr.imag) > 1.0)))
+    assert abs(mean[6] - msign) <= 2.0 * flips / B + 1e-12
+    if flips == 0:
+        scale = 1.0 + (np.abs(est[:, :, 0]) * (ko + kd[:, None])).mean()
+        assert np.max(np.abs(got - want)) < TOL[prec] * scale / abs(msign)
+
+
+@pytest.mark.parametrize("seed,scale,mul", [(94, "stress", 1.0), (91, "stress", 1.5)])
+def test_exhaustive_enumeration_n4(gpu, seed, scale, mul):
+    """All 16 alpha at n = 4: sum rho(a,a) A~(a) / sum rho(a,a) from the GPU's
+    local estimators and diagonal equals the oracle's enumeration (FP32).  The
+    bound propagates each sample's error (relative TOL k_d on rho(a,a), the
+    local-estimator bound on A~) through the ratio of sums.  Seed 94 has a
+    positive diagonal (no cancellation in the trace); seed 91 at 1.5x is far
+    from positive, and its trace cancels about a hundredfold."""
+    arch = SMALL
+    n = 4
+    params = (synth.params(arch, seed, scale) * mul).astype(np.float32)
+    a = np.arange(1 << n, dtype=np.uint64)
+    ctx = gpu.Ctx(0)
+    lrd, local, _ = ctx.observables(arch, cuda(params), n, cuda(a), "fp32", want_mean=False)
+    lrd, local = lrd.cpu().numpy().astype(np.float64), local.cpu().numpy().astype(np.float64)
+    d = np.exp(lrd[:, 0] - lrd[:, 0].max()) * np.where(np.abs(lrd[:, 1]) > 1.0, -1.0, 1.0)
+    got = (d[:, None] * (local[:, :, 0] + 1j * local[:, :, 1])).sum(axis=0) / d.sum()
+    f = ob.ansatz_log_rho(params.astype(np.float64), oa.Arch(**arch), n)
+    want = ob.enumerated_expectation(f, n).mean(axis=0)
+    est, lr, kd, ko = oracle_local(params, arch, n, a)
+    check_local(local.astype(np.float32), lrd.astype(np.float32), (est, lr, kd, ko), "fp32", "all alpha, n = 4")
+    tol = TOL["fp32"]
+    avg = np.abs(est.mean(axis=1))                                      # [16, 3]
+    e_loc = tol * (1.0 + (np.abs(est[:, :, 0]) * (ko + kd[:, None])).mean(axis=1))
+    e_d = tol * kd
+    bound = (np.abs(d)[:, None] * (e_d[:, None] * (avg + np.abs(want)[None, :]) + e_loc[:, None])).sum(axis=0) \
+        / abs(d.sum())
+    cond = np.abs(d).sum() / abs(d.sum())
+    print(f"enumerated <sigma> GPU {got}, oracle {want}, cancellation of the trace {cond:.1f}, bound {bound}")
+    assert np.all(np.abs(got - want) < bound)
+
+
+def test_full_size_sampled(gpu):
+    """The Ising n = 32 network (d = 64, 8 heads, 4 layers, MLP 256), 8192
+    samples (270336 network rows) in BF16 and FP32; 12 sampled outputs are
+    recomputed by the oracle."""
+    wl = synth.workload("ising_n32")
+    arch, n = wl["arch"], wl["model"]["n"]
+    params = synth.params(arch, wl["seed"], "mid")
+    B = 8192
+    a = alphas(n, B, 77)
+    ctx = gpu.Ctx(0)
+    pick = np.sort(np.random.default_rng(5).choice(B, 12, replace=False))
+    ref = oracle_local(params, arch, n, a[pick])
+    for prec in ("fp32", "bf16"):
+        lrd, local, mean = ctx.observables(arch, cuda(params), n, cuda(a), prec)
+        lrd, local, mean = lrd.cpu().numpy(), local.cpu().numpy(), mean.cpu().numpy()
+        assert np.all(np.isfinite(local)) and np.all(np.isfinite(mean))
+        check_local(local[pick], lrd[pick], ref, prec, f"ising_n32 B={B}")
+
+
+def test_chunked_equals_unchunked(gpu):
+    """A small workspace budget splits the samples into many chunks; the outputs
+    are bit-identical to one chunk, and so are the fixed-order means."""
+    arch = synth.WORKLOADS["ising_n8"]["arch"]
+    n, B = 8, 3000
+    params = cuda(synth.params(arch, 3, "stress"))
+    a = cuda(alphas(n, B, 4))
+    big = gpu.Ctx(0)
+    small = gpu.Ctx(0, 6 << 20)
+    r1 = big.observables(arch, params, n, a, "bf16")
+    r2 = small.observables(arch, params, n, a, "bf16")
+    for x, y in zip(r1, r2):
+        assert torch.equal(x, y)
+
+
+def test_degenerate_and_invalid(gpu):
+    arch = SMALL
+    n = 4
+    params = cuda(synth.params(arch, 1, "mid"))
+    ctx = gpu.Ctx(0)
+    e = torch.zeros((0,), dtype=torch.uint64, device="cuda")
+    lrd, local, _ = ctx.observables(arch, params, n, e, "fp32", want_mean=False)
+    assert lrd.shape == (0, 2) and local.shape == (0, 3, 2)
+    with pytest.raises(gpu.TdoError):
+        ctx.observables(arch, params, n, e, "fp32", want_mean=True)   # a mean over no samples
+    with pytest.raises(gpu.TdoError):
+        ctx.purity(arch, params, n, e, e)
+    s, ctr = ctx.sample_diag(arch, params, n, e, torch.zeros((0, 2), dtype=torch.float32, device="cuda"), 1, 5, 3)
+    assert s.shape == (3, 0) and ctr == 5 + 3 * n
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_purity_pairs(gpu, prec):
+    """Pairs from two sets of samples: the GPU's pair estimator equals the
+    oracle's on the same pairs.  out[0] out[1]^2 is the mean term, bounded like
+    the estimators: a term t = exp(2 Re l_ab - Re l_aa - Re l_bb) moves by
+    t TOL (2 k_ab + k_aa + k_bb); the mean sign moves only where a diagonal's
+    sign lies within its error."""
+    arch = synth.WORKLOADS["ising_n8"]["arch"]
+    n, P = 8, 1500
+    params = synth.params(arch, 17, "stress")
+    a, b = alphas(n, P, 18), alphas(n, P, 19)
+    ctx = gpu.Ctx(0)
+    out = ctx.purity(arch, cuda(params), n, cuda(a), cuda(b), prec).cpu().numpy()
+    f = ob.ansatz_log_rho(params.astype(np.float64), oa.Arch(**arch), n)
+    ab, aa, bb = np.stack([a, b], 1), np.stack([a, a], 1), np.stack([b, b], 1)
+    lab, laa, lbb = f(ab), f(aa), f(bb)
+    want = ob.sampled_purity(lab, laa, lbb)
+    t = ob.purity_terms(lab, laa, lbb)
+    k = [cancellation(params, arch, n, c) for c in (ab, aa, bb)]
+    s = np.concatenate([ob.diagonal_sign(laa), ob.diagonal_sign(lbb)])
+    unsure = np.sum(np.concatenate([k[1], k[2]]) * TOL[prec] >= 0.5)
+    bound_t = TOL[prec] * np.mean(t * (2 * k[0] + k[1] + k[2]))
+    got_t = out[0] * out[1] ** 2
+    print(f"purity {prec}: GPU {out[0]:.6e} oracle {want:.6e}; mean term {got_t:.6e} vs {t.mean():.6e} "
+          f"(bound {bound_t:.2e}); mean sign {out[1]:.4f} vs {s.mean():.4f}")
+    assert abs(got_t - t.mean()) < bound_t
+    assert abs(out[1] - s.mean()) <= 2.0 * unsure / (2 * P) + 1e-12
+    if prec == "fp32":
+        assert abs(out[0] - want) < 1e-3 * want
+
+
+def gpu_diag_chains(ctx, arch, params, n, st, seed, counter, sweeps, prec="fp32"):
+    p = cuda(params)
+    state = cuda(st)
+    lr = ctx.log_rho(arch, p, n, cuda(np.stack([st, st], 1)), prec)
+    samples, ctr = ctx.sample_diag(arch, p, n, state, lr, seed, counter, sweeps, prec)
+    return samples.cpu().numpy(), ctr
+
+
+def test_diag_random_walk_bit_exact(gpu):
+    """Zero weights: every proposal is accepted; the chains are the proposal walk."""
+    n, C, sweeps = 7, 300, 3
+    params = np.zeros(synth.num_params(SMALL), np.float32)
+    st = alphas(n, C, 8)
+    ctx = gpu.Ctx(0)
+    got, ctr = gpu_diag_chains(ctx, SMALL, params, n, st, 0xABCDEF0123, 9, sweeps)
+    f = ob.ansatz_log_rho(params.astype(np.float64), oa.Arch(**SMALL), n)
+    ref, _, _, ctr_ref = ob.diag_metropolis(f, n, st, f(np.stack([st, st], 1)), 0xABCDEF0123, 9, sweeps)
+    assert ctr == ctr_ref == 9 + sweeps * n
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name,n,C,sweeps", [("ising_n4", 6, 256, 4), ("xyz_n16", 11, 128, 2)])
+def test_diag_chains_follow_oracle(gpu, name, n, C, sweeps):
+    """Chains agree with the oracle's step by step; a chain may leave it only
+    after an acceptance decision within MARGIN of the boundary."""
+    arch = synth.WORKLOADS[name]["arch"]
+    params = synth.params(arch, 700 + n, "stress")
+    st = alphas(n, C, 701 + n)
+    ctx = gpu.Ctx(0)
+    got, _ = gpu_diag_chains(ctx, arch, params, n, st, 31, 0, sweeps)
+    f = ob.ansatz_log_rho(params.astype(np.float64), oa.Arch(**arch), n)
+    state = st.copy()
+    lr = f(np.stack([state, state], 1))
+    ref = np.zeros((sweeps, C), np.uint64)
+    first_marginal = np.full(C, 1 << 30)
+    t = 0
+    for s in range(sweeps):
+        for _ in range(n):
+            prop, u = ob.diag_proposal(state, n, t, np.arange(C), 31)
+            lrp = f(np.stack([prop, prop], 1))
+            with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+                gap = np.abs(np.log(u) - (lrp.real - lr.real))
+                acc = u < np.exp(lrp.real - lr.real)
+            gap = np.where(np.isfinite(gap), gap, np.inf)
+            first_marginal = np.where((gap < MARGIN) & (first_marginal > t), t, first_marginal)
+            state[acc] = prop[acc]
+            lr[acc] = lrp[acc]
+            t += 1
+        ref[s] = state
+    same = got == ref
+    diverged = ~np.all(same, axis=0)
+    first_bad = np.argmax(~same, axis=0)
+    for c in np.nonzero(diverged)[0]:
+        assert first_marginal[c] < (first_bad[c] + 1) * n, (c, first_marginal[c], first_bad[c])
+    print(f"{name} n={n}: {int(diverged.sum())} of {C} diagonal chains left the oracle after a marginal decision")
+    assert diverged.mean() < 0.05
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_diag_visit_frequencies(gpu, prec):
+    """n = 4, 4096 chains: visit frequencies follow |rho(a,a)| / sum |rho(a,a)|
+    (FP64 oracle for FP32; the BF16 rounding emulation for BF16)."""
+    arch = SMALL
+    n = 4
+    params = (synth.params(arch, 93, "stress") * 1.5).astype(np.float32)
+    a_all = np.arange(1 << n, dtype=np.uint64)
+    cfg = np.stack([a_all, a_all], 1)
+    if prec == "fp32":
+        lr = ob.ansatz_log_rho(params.astype(np.float64), oa.Arch(**arch), n)(cfg)
+    else:
+        lr = log_rho_emulated(params, oa.Arch(**arch), cfg, n, "bf16")
+    p = np.exp(lr.real - lr.real.max())
+    p /= p.sum()
+    C = 4096
+    st = alphas(n, C, 94)
+    ctx = gpu.Ctx(0)
+    pt, state = cuda(params), cuda(st)
+    slr = ctx.log_rho(arch, pt, n, cuda(np.stack([st, st], 1)), prec)
+    _, ctr = ctx.sample_diag(arch, pt, n, state, slr, 5, 0, 20, prec)           # burn-in
+    samples, _ = ctx.sample_diag(arch, pt, n, state, slr, 5, ctr, 40, prec)
+    counts = np.bincount(samples.cpu().numpy()[3::4].reshape(-1).astype(np.int64), minlength=1 << n)
+    expect = p * counts.sum()
+    keep = expect > 5
+    chi2 = np.sum((counts[keep] - expect[keep]) ** 2 / expect[keep])
+    sf = stats.chi2.sf(chi2 / 2.0, keep.sum() - 1)
+    print(f"diagonal chain {prec}: chi-square survival {sf:.3e} over {keep.sum()} states")
+    assert sf > 1e-4
+
+
+def test_diag_full_size_sampled_chains(gpu):
+    """Ising n = 32 network, 65536 diagonal chains for one sweep (32 proposals);
+    12 sampled chains are replayed by the oracle."""
+    wl = synth.workload("ising_n32")
+    arch, n = wl["arch"], wl["model"]["n"]
+    params = synth.params(arch, wl["seed"], "mid")
+    C = 65536
+    st = alphas(n, C, 3100)
+    ctx = gpu.Ctx(0)
+    got, ctr = gpu_diag_chains(ctx, arch, params, n, st, 99, 13, 1, "fp32")
+    assert ctr == 13 + n
+    f = ob.ansatz_log_rho(params.astype(np.float64), oa.Arch(**arch), n)
+    for c in np.sort(np.random.default_rng(6).choice(C, 12, replace=False)):
+        state = st[c:c + 1].copy()
+        lr = f(np.stack([state, state], 1))
+        marginal = False
+        for t in range(13, 13 + n):
+            prop, u = ob.diag_proposal(state, n, t, np.array([c]), 99)
+            lrp = f(np.stack([prop, prop], 1))
+            d = float(lrp.real[0] - lr.real[0])
+            marginal |= abs(math.log(u[0]) - d) < MARGIN
+            if u[0] < math.exp(min(d, 700.0)):
+                state, lr = prop, lrp
+        if not marginal:
+            assert got[0, c] == state[0], c
