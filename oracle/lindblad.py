@@ -25,6 +25,13 @@ Conventions (fixed by the paper's own closed forms)
   rho_11 = (1+g^2)/(1+2g^2) (Ising section, single-qubit closed form).
 * site i of a configuration is bit i of the packed integer; bonds are periodic,
   (i, i+1 mod N).
+* 2D Ising (the 2D dissipative Ising paragraph of the results, and its 2 x 2
+  companion in the supplement): an M x C periodic square lattice (M = rows > 1)
+  with n = M C sites numbered row-major, site (r, c) = bit r C + c.  The sum
+  over nearest-neighbour pairs <ij> runs over distinct unordered pairs, each
+  once: a ring of length 2 has one bond, a ring of length 1 none, so the 2 x 2
+  lattice has the 4 bonds the paper counts.  Only the Ising model is defined on
+  the lattice.
 * a two-site local matrix kron(A, B) on sites (i, j) is indexed by
   2*bit_i + bit_j.
 * Hamiltonians, read literally with Pauli matrices:
@@ -70,7 +77,27 @@ class Model:
     By: float = 0.0
     Bz: float = 0.0
     gamma: float = 1.0
+    rows: int = 1
     extra: dict = field(default_factory=dict)
+
+
+def bonds(model: Model):
+    """The bond list: (i, i+1 mod n) for a chain (rows <= 1); for an M x C
+    lattice the distinct nearest-neighbour pairs of the periodic square lattice."""
+    n, M = model.n, max(1, int(model.rows))
+    if M == 1:
+        return [(i, (i + 1) % n) for i in range(n)]
+    if n % M:
+        raise ValueError(f"n={n} is not a multiple of rows={M}")
+    C = n // M
+    out = []
+    for r in range(M):
+        for c in range(C):
+            i = r * C + c
+            for j in (r * C + (c + 1) % C, ((r + 1) % M) * C + c):
+                if j != i and (min(i, j), max(i, j)) not in out:
+                    out.append((min(i, j), max(i, j)))
+    return out
 
 
 def operator_terms(model: Model):
@@ -78,7 +105,8 @@ def operator_terms(model: Model):
 
     Returns (ham, jumps): ham is a list of (sites, matrix) with matrix of size
     2^len(sites); jumps is a list of (site, matrix, rate).
-    Ising section: H = (V/4) sum sz sz + (g/2) sum sx, L_i = sigma^-_i.
+    Ising section: H = (V/4) sum sz sz + (g/2) sum sx, L_i = sigma^-_i, the
+    sum over the bonds of the chain or of the 2D lattice.
     Heisenberg section: H = sum_i sum_k J_k sk_i sk_{i+1} + B_k sk_i.
     """
     n = model.n
@@ -91,11 +119,13 @@ def operator_terms(model: Model):
         site = model.Bx * SX + model.By * SY + model.Bz * SZ
     else:
         raise ValueError(f"unknown model kind {model.kind}")
+    if model.rows > 1 and model.kind != ISING:
+        raise ValueError("only the Ising model is defined on a 2D lattice")
     if np.any(bond != 0):
         if n < 2:
             raise ValueError("a bond term needs n >= 2")
-        for i in range(n):
-            ham.append(((i, (i + 1) % n), bond))
+        for b in bonds(model):
+            ham.append((b, bond))
     if np.any(site != 0):
         for i in range(n):
             ham.append(((i,), site))

@@ -23,9 +23,32 @@ def site_op(ops: dict, n: int) -> np.ndarray:
     return reduce(np.kron, [ops.get(i, I2) for i in range(n)])
 
 
-def hamiltonian(kind, n, V=0.0, g=0.0, Jx=0.0, Jy=0.0, Jz=0.0, Bx=0.0, By=0.0, Bz=0.0):
+def torus_neighbours(M, C):
+    """Nearest-neighbour pairs of an M x C periodic square lattice, sites row-major,
+    as a set of unordered pairs: the four lattice neighbours of each site, with the
+    pairs that coincide (rings of length 2) or are self-pairs (length 1) counted once
+    or not at all."""
+    out = set()
+    for r in range(M):
+        for c in range(C):
+            for dr_, dc in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+                j = ((r + dr_) % M) * C + (c + dc) % C
+                i = r * C + c
+                if i != j:
+                    out.add(frozenset((i, j)))
+    return sorted(tuple(sorted(p)) for p in out)
+
+
+def hamiltonian(kind, n, V=0.0, g=0.0, Jx=0.0, Jy=0.0, Jz=0.0, Bx=0.0, By=0.0, Bz=0.0, lattice=None):
     D = 1 << n
     H = np.zeros((D, D), np.complex128)
+    if lattice is not None:                      # 2D Ising on an M x C torus
+        assert kind == 0
+        for i, j in torus_neighbours(*lattice):
+            H += (V / 4) * site_op({i: PZ, j: PZ}, n)
+        for i in range(n):
+            H += (g / 2) * site_op({i: PX}, n)
+        return H
     for i in range(n):
         j = (i + 1) % n
         if kind == 0:
