@@ -157,7 +157,8 @@ def main():
     if args.lindblad_only or args.batched_only or args.sampler_only or args.observables_only:
         if args.observables_only:
             line = {"metric": "mixed-state observables, samples/s",
-                    "observables": bench_observables(ctx, arch, params, n, synth)}
+                    "observables": bench_observables(ctx, arch, params, n, synth),
+                    "ising2d_4x8": bench_lattice2d(ctx, synth)}
         elif args.lindblad_only:
             line = {"metric": "Lindbladian rows and L_loc, algorithmic HBM GB/s",
                     "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
@@ -220,6 +221,7 @@ def main():
                   "batched_uneven": bench_batched(ctx, tdo, synth, args.steps),
                   "sampler": bench_sampler(ctx, arch, params, n, synth),
                   "observables": bench_observables(ctx, arch, params, n, synth),
+                  "ising2d_4x8": bench_lattice2d(ctx, synth),
                   "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
 
     # the oracle leg (host): timed on a bounded sample, and (unless --no-check) the FP64 loss of
@@ -378,6 +380,30 @@ def bench_sampler(ctx, arch, params, n, synth):
     props = C * 2 * n
     log(f"bench: sampler {C} chains x {2 * n} proposals in {ms:.1f} ms: {props / ms * 1e3 / 1e6:.2f} M proposals/s")
     return {"value": props / (ms / 1e3), "unit": "proposals/s", "chains": C, "sweeps": 1, "ms": ms, "dtype": "bf16"}
+
+
+def bench_lattice2d(ctx, synth, B=16384):
+    """The 2D dissipative Ising model on a 4 x 8 periodic lattice (n = 32) with the
+    benchmark network, BF16 loss and gradient (mode B) over B = 16384 samples: the
+    same kernels as the chain with the lattice's bond sum in the diagonal entries."""
+    import torch
+    wl = synth.workload("ising2d_4x8")
+    arch, model = wl["arch"], wl["model"]
+    params = torch.from_numpy(synth.params(arch, wl["seed"], "init")).cuda()
+    cfg = torch.from_numpy(synth.configs(model["n"], B, 3000)).cuda()
+    E = evaluated_configs(ctx, model, cfg)
+    ctx.loss_grad(arch, params, model, cfg, None, "bf16", "B")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        ctx.loss_grad(arch, params, model, cfg, None, "bf16", "B")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    log(f"bench: ising2d_4x8 B={B} ({E} configurations): loss+gradient bf16 {E / ms * 1e3 / 1e6:.3f} M/s")
+    return {"lattice": [4, 8], "n": model["n"], "B": B, "configs_per_step": E, "ms_per_step": ms,
+            "configs_per_s": E / (ms / 1e3), "dtype": "bf16"}
 
 
 def bench_observables(ctx, arch, params, n, synth):

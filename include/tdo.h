@@ -54,10 +54,16 @@ typedef struct {
 /* Dissipative spin chain with periodic bonds and jumps sqrt(gamma) sigma^-_i.
  * kind 0: Ising,  H = (V/4) sum sz_i sz_{i+1} + (g/2) sum sx_i  (Ising section)
  * kind 1: XYZ,    H = sum_i sum_k J_k sk_i sk_{i+1} + B_k sk_i   (Heisenberg section)
- * Fields Bx, By, Bz are used by kind 1 only; kind 0 ignores J*, B*. */
+ * Fields Bx, By, Bz are used by kind 1 only; kind 0 ignores J*, B*.
+ * rows: 0 or 1 for a chain.  rows = M > 1 (kind 0 only, n a multiple of M)
+ * places the n sites on an M x (n/M) periodic square lattice, row-major
+ * (site (r, c) is bit r (n/M) + c), and sums sz sz over its distinct
+ * nearest-neighbour pairs (2D dissipative Ising paragraph of the results; a
+ * ring of length 2 has one bond).  The network sees the sites in that order. */
 typedef struct {
     int32_t kind, n;
     double V, g, Jx, Jy, Jz, Bx, By, Bz, gamma;
+    int32_t rows;
 } tdo_model_t;
 
 typedef enum { TDO_FP32 = 0, TDO_BF16 = 1 } tdo_prec_t;

@@ -9,7 +9,11 @@ namespace tdo {
 struct ModelDev {
   int kind, n, nslots, has_fields;
   int gamma_ok, hmove_eq, hmove_ne;
+  int rows, cols;  // rows = 1: chain; otherwise an M x C periodic lattice, row-major
   double gam, gam2, V4, g2, Jz, jm, jp, Bx, By, Bz;
+  // lattice masks: sites in the last column, the other sites, the first column,
+  // and the first row
+  uint64_t h_last, h_keep, h_first, low_cols;
 };
 
 int32_t make_model(const tdo_model_t* m, ModelDev* out);

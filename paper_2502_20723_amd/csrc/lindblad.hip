@@ -3,8 +3,8 @@
 //
 // Row x = (alpha, beta) of Lhat = -i(H (x) 1 - 1 (x) H^T)
 //   + sum_j gamma [L_j (x) L_j^* - 1/2 L_j^dag L_j (x) 1 - 1/2 1 (x) L_j^T L_j^*]
-// (Eq. VecLin; App. A) for H of the Ising section or of the Heisenberg
-// section and L_j = sigma^-_j.  Worked out per slot type:
+// (Eq. VecLin; App. A) for H of the Ising section (chain or 2D lattice) or of
+// the Heisenberg section and L_j = sigma^-_j.  Worked out per slot type:
 //   diagonal   -i[E(alpha) - E(beta)] - (gamma/2) (#up(alpha) + #up(beta)),
 //              E the diagonal of H (Ising (V/4) sum s s; XYZ Jz sum s s + Bz sum s)
 //   alpha move H(alpha, alpha') with a minus i:  Ising flip of site i, -i g/2;
@@ -24,9 +24,22 @@ int32_t make_model(const tdo_model_t* m, ModelDev* out) {
   TDO_CHECK(m != nullptr, TDO_EINVAL, "model is NULL");
   TDO_CHECK(m->kind == 0 || m->kind == 1, TDO_EINVAL, "model kind %d is not 0 (Ising) or 1 (XYZ)", m->kind);
   TDO_CHECK(m->n >= 3 && m->n <= 64, TDO_EINVAL, "chain length n=%d outside [3, 64]", m->n);
+  TDO_CHECK(m->rows >= 0, TDO_EINVAL, "rows=%d < 0", m->rows);
   ModelDev d{};
   d.kind = m->kind;
   d.n = m->n;
+  d.rows = m->rows > 1 ? m->rows : 1;
+  if (d.rows > 1) {
+    TDO_CHECK(m->kind == 0, TDO_EINVAL, "a lattice (rows=%d) is defined for the Ising model only", m->rows);
+    TDO_CHECK(m->n % d.rows == 0, TDO_EINVAL, "n=%d is not a multiple of rows=%d", m->n, m->rows);
+  }
+  d.cols = d.n / d.rows;
+  for (int r = 0; r < d.rows; ++r) {
+    d.h_last |= 1ull << (r * d.cols + d.cols - 1);
+    d.h_first |= 1ull << (r * d.cols);
+  }
+  d.h_keep = low_mask(d.n) & ~d.h_last;
+  d.low_cols = low_mask(d.cols);
   d.gam = m->gamma;
   d.gam2 = 0.5 * m->gamma;
   d.gamma_ok = m->gamma != 0.0;
@@ -75,6 +88,11 @@ __device__ __forceinline__ double in_reg(double v) {
 // after a batch of loads, it keeps the compiler from waiting for all outstanding stores at the
 // first use of those loads inside a loop (the counter is shared and in order).
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+__device__ __forceinline__ uint64_t in_reg(uint64_t v) {
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (hi << 32) | lo;
+}
 
 __device__ __forceinline__ ModelDev in_regs(const ModelDev& m) {
   ModelDev r;
@@ -82,7 +100,38 @@ __device__ __forceinline__ ModelDev in_regs(const ModelDev& m) {
   r.gamma_ok = in_reg(m.gamma_ok); r.hmove_eq = in_reg(m.hmove_eq); r.hmove_ne = in_reg(m.hmove_ne);
   r.gam = in_reg(m.gam); r.gam2 = in_reg(m.gam2); r.V4 = in_reg(m.V4); r.g2 = in_reg(m.g2); r.Jz = in_reg(m.Jz);
   r.jm = in_reg(m.jm); r.jp = in_reg(m.jp); r.Bx = in_reg(m.Bx); r.By = in_reg(m.By); r.Bz = in_reg(m.Bz);
+  r.rows = in_reg(m.rows); r.cols = in_reg(m.cols);
+  r.h_last = in_reg(m.h_last); r.h_keep = in_reg(m.h_keep); r.h_first = in_reg(m.h_first);
+  r.low_cols = in_reg(m.low_cols);
   return r;
+}
+
+// sum over the bonds of s_i s_j = (number of bonds) - 2 (bonds whose spins differ).
+// Chain: bonds (i, i+1 mod n).  M x C lattice: the right neighbour within the row
+// and the neighbour one row down, each distinct pair once (a ring of length 2 has
+// one bond, a ring of length 1 none).
+__device__ __forceinline__ int bond_sum(const ModelDev& m, uint64_t a) {
+  const int n = m.n;
+  if (m.rows == 1) return n - 2 * __popcll(a ^ rot_down(a, n));
+  const int M = m.rows, C = m.cols;
+  int nb = 0, nd = 0;
+  if (C >= 3) {  // bit i of r: the right neighbour's spin, wrapping within the row
+    const uint64_t r = ((a >> 1) & m.h_keep) | ((a << (C - 1)) & m.h_last);
+    nd += __popcll(a ^ r);
+    nb += n;
+  } else if (C == 2) {
+    nd += __popcll((a ^ (a >> 1)) & m.h_first);
+    nb += M;
+  }
+  if (M >= 3) {  // bit i of r: the spin one row down, wrapping
+    const uint64_t r = ((a >> C) | (a << (n - C))) & low_mask(n);
+    nd += __popcll(a ^ r);
+    nb += n;
+  } else {  // M == 2
+    nd += __popcll((a ^ (a >> C)) & m.low_cols);
+    nb += C;
+  }
+  return nb - 2 * nd;
 }
 
 __device__ bool slot_entry(const ModelDev& m, uint64_t a, uint64_t b, int s, uint64_t& ya,
@@ -95,8 +144,8 @@ __device__ bool slot_entry(const ModelDev& m, uint64_t a, uint64_t b, int s, uin
   yb = b;
   if (s == 0) {
     int nup = 2 * n - __popcll(a) - __popcll(b);
-    int bsa = n - 2 * __popcll(a ^ rot_down(a, n));
-    int bsb = n - 2 * __popcll(b ^ rot_down(b, n));
+    int bsa = bond_sum(m, a);
+    int bsb = bond_sum(m, b);
     double re = -m.gam2 * (double)nup, im;
     bool im_zero;
     if (m.kind == 0) {

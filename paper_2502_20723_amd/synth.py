@@ -44,6 +44,12 @@ WORKLOADS = {
     "ising_n32": dict(model=dict(kind=ISING, n=32, V=2.0, g=None, gamma=1.0),
                       arch=arch(64, 8, 4, 256), B=65536, seed=1003),
     "batched_uneven": dict(model=None, arch=arch(64, 4, 3, 256), B=2048, seed=1004, problems=64),
+    # 2D dissipative Ising: the paper's 2 x 3 lattice (V = 2 gamma) with the small
+    # network, and a 4 x 8 lattice (n = 32) with the benchmark network
+    "ising2d_2x3": dict(model=dict(kind=ISING, n=6, rows=2, V=2.0, g=1.0, gamma=1.0),
+                        arch=arch(16, 2, 1, 64), B=1024, seed=1005),
+    "ising2d_4x8": dict(model=dict(kind=ISING, n=32, rows=4, V=2.0, g=1.0, gamma=1.0),
+                        arch=arch(64, 8, 4, 256), B=65536, seed=1006),
 }
 
 

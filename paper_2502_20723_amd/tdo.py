@@ -31,7 +31,8 @@ class ArchT(ctypes.Structure):
 
 class ModelT(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32)] + [
-        (k, ctypes.c_double) for k in ("V", "g", "Jx", "Jy", "Jz", "Bx", "By", "Bz", "gamma")]
+        (k, ctypes.c_double) for k in ("V", "g", "Jx", "Jy", "Jz", "Bx", "By", "Bz", "gamma")] + [
+        ("rows", ctypes.c_int32)]
 
 
 class TdoError(RuntimeError):
@@ -93,7 +94,7 @@ def arch_t(a: dict) -> ArchT:
 def model_t(m: dict) -> ModelT:
     return ModelT(int(m["kind"]), int(m["n"]), *[float(m.get(k, 0.0) or 0.0) for k in
                                                  ("V", "g", "Jx", "Jy", "Jz", "Bx", "By", "Bz")],
-                  float(m.get("gamma", 1.0)))
+                  float(m.get("gamma", 1.0)), int(m.get("rows", 1) or 1))
 
 
 def num_params(a: dict) -> int:
