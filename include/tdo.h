@@ -254,6 +254,27 @@ int32_t tdo_purity(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, 
                    const uint64_t *alpha, const uint64_t *beta, int64_t P, tdo_prec_t prec,
                    double *out, hipStream_t stream);
 
+/* Learning rate of the training loop (App. C, learning-rate scheduling): eta0
+ * for step < i_switch, then eta0 (1 + cos(pi x)) / 2 + alpha eta0 with
+ * x = min(1, (step - i_switch) / i_decay) (the rate stays at alpha eta0 after
+ * the decay period).  Host code: needs no device. */
+double tdo_lr_schedule(int64_t step, double eta0, int64_t i_switch, int64_t i_decay, double alpha);
+
+/* First-order update theta <- theta - lr grad (App. C, optimisation procedure,
+ * SGD).  params: device float [P] in/out; grad: device double [P] (as written
+ * by tdo_loss_grad).  Formed in FP64, rounded once to FP32.  P >= 0. */
+int32_t tdo_sgd_step(int64_t P, float *params, const double *grad, double lr, hipStream_t stream);
+
+/* Adam update (App. C, optimisation procedure; Kingma and Ba, ICLR 2015,
+ * Algorithm 1) at step t >= 1: m <- beta1 m + (1 - beta1) g,
+ * v <- beta2 v + (1 - beta2) g^2, theta <- theta - lr m_hat / (sqrt(v_hat) + eps)
+ * with m_hat = m / (1 - beta1^t), v_hat = v / (1 - beta2^t).  params: device
+ * float [P] in/out; grad: device double [P]; m, v: device double [P] in/out,
+ * zero before step 1.  0 <= beta < 1, eps > 0.  Formed in FP64 without fused
+ * multiply-adds, rounded once to FP32. */
+int32_t tdo_adam_step(int64_t P, float *params, const double *grad, double *m, double *v, int64_t t,
+                      double lr, double beta1, double beta2, double eps, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

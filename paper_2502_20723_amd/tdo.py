@@ -22,7 +22,7 @@ PREC = {"fp32": TDO_FP32, "bf16": TDO_BF16}
 EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_error", "tdo_profile",
            "tdo_profile_read", "tdo_connected", "tdo_local_lindbladian", "tdo_log_rho", "tdo_log_rho_vjp",
            "tdo_loss_grad", "tdo_loss_grad_batched", "tdo_sample", "tdo_sample_diag", "tdo_observables",
-           "tdo_purity")
+           "tdo_purity", "tdo_lr_schedule", "tdo_sgd_step", "tdo_adam_step")
 
 
 class ArchT(ctypes.Structure):
@@ -73,9 +73,15 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_uint64), i32, i32, vp, vp]
         L.tdo_observables.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp, vp, vp]
         L.tdo_purity.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, vp, i64, i32, vp, vp]
+        dbl = ctypes.c_double
+        L.tdo_lr_schedule.argtypes = [i64, dbl, i64, i64, dbl]
+        L.tdo_sgd_step.argtypes = [i64, vp, vp, dbl, vp]
+        L.tdo_adam_step.argtypes = [i64, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, vp]
         for name in EXPORTS:
-            if name not in ("tdo_last_error", "tdo_num_params", "tdo_ctx_create", "tdo_ctx_destroy"):
+            if name not in ("tdo_last_error", "tdo_num_params", "tdo_ctx_create", "tdo_ctx_destroy",
+                            "tdo_lr_schedule"):
                 getattr(L, name).restype = i32
+        L.tdo_lr_schedule.restype = ctypes.c_double
         L.tdo_ctx_create.restype = i32
         L.tdo_ctx_destroy.restype = i32
         _lib = L
@@ -95,6 +101,29 @@ def model_t(m: dict) -> ModelT:
     return ModelT(int(m["kind"]), int(m["n"]), *[float(m.get(k, 0.0) or 0.0) for k in
                                                  ("V", "g", "Jx", "Jy", "Jz", "Bx", "By", "Bz")],
                   float(m.get("gamma", 1.0)), int(m.get("rows", 1) or 1))
+
+
+def lr_schedule(step: int, eta0: float, i_switch: int, i_decay: int, alpha: float) -> float:
+    return float(lib().tdo_lr_schedule(step, eta0, i_switch, i_decay, alpha))
+
+
+def sgd_step(params, grad, lr: float):
+    """In place: params (device float32 [P]) -= lr grad (device float64 [P])."""
+    P = params.shape[0]
+    _dev(params, torch.float32, (P,), "params")
+    _dev(grad, torch.float64, (P,), "grad")
+    _check(lib().tdo_sgd_step(P, _ptr(params), _ptr(grad), lr, _stream()))
+
+
+def adam_step(params, grad, m, v, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In place: one Adam step on params (device float32 [P]) with moments m, v
+    (device float64 [P], zero before t = 1)."""
+    P = params.shape[0]
+    _dev(params, torch.float32, (P,), "params")
+    for x, nm in ((grad, "grad"), (m, "m"), (v, "v")):
+        _dev(x, torch.float64, (P,), nm)
+    _check(lib().tdo_adam_step(P, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), t, lr, beta1, beta2, eps,
+                               _stream()))
 
 
 def num_params(a: dict) -> int:
