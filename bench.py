@@ -158,7 +158,8 @@ def main():
         if args.observables_only:
             line = {"metric": "mixed-state observables, samples/s",
                     "observables": bench_observables(ctx, arch, params, n, synth),
-                    "ising2d_4x8": bench_lattice2d(ctx, synth)}
+                    "ising2d_4x8": bench_lattice2d(ctx, synth),
+                    "sr": bench_sr(ctx, arch, params, n, synth)}
         elif args.lindblad_only:
             line = {"metric": "Lindbladian rows and L_loc, algorithmic HBM GB/s",
                     "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
@@ -222,6 +223,7 @@ def main():
                   "sampler": bench_sampler(ctx, arch, params, n, synth),
                   "observables": bench_observables(ctx, arch, params, n, synth),
                   "ising2d_4x8": bench_lattice2d(ctx, synth),
+                  "sr": bench_sr(ctx, arch, params, n, synth),
                   "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
 
     # the oracle leg (host): timed on a bounded sample, and (unless --no-check) the FP64 loss of
@@ -380,6 +382,40 @@ def bench_sampler(ctx, arch, params, n, synth):
     props = C * 2 * n
     log(f"bench: sampler {C} chains x {2 * n} proposals in {ms:.1f} ms: {props / ms * 1e3 / 1e6:.2f} M proposals/s")
     return {"value": props / (ms / 1e3), "unit": "proposals/s", "chains": C, "sweeps": 1, "ms": ms, "dtype": "bf16"}
+
+
+def bench_sr(ctx, arch, params, n, synth, B=256, iters=100):
+    """Stochastic reconfiguration with the n = 32 network: the per-sample Jacobian of
+    B = 256 samples (2B backward passes, FP32), then 100 conjugate-gradient
+    iterations of (S + lambda I) x = g with S = J^T J applied as two passes over
+    J (2B x P FP64).  Algorithmic HBM bytes per iteration: 2 x 2B x P x 8 (J read
+    twice) plus the vectors."""
+    import numpy as np
+    import torch
+    P = params.shape[0]
+    cfg = torch.from_numpy(synth.configs(n, B, 7000)).cuda()
+    g = torch.from_numpy(np.random.default_rng(7001).standard_normal(P)).cuda()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), out
+
+    ctx.jacobian(arch, params, n, cfg[:2], "fp32")
+    ms_j, J = timed(lambda: ctx.jacobian(arch, params, n, cfg, "fp32"))
+    ctx.sr_solve(J.clone(), g, 1e-3, 2)
+    ms_s, (x, info) = timed(lambda: ctx.sr_solve(J, g, 1e-3, iters))
+    res = float(info.cpu()[0])
+    it_bytes = 2 * (2 * B) * P * 8 + 6 * P * 8
+    gbs = iters * it_bytes / (ms_s / 1e3) / 1e9
+    log(f"bench: SR n={n} B={B} P={P}: jacobian {ms_j:.1f} ms ({2 * B / (ms_j / 1e3):.0f} rows/s), "
+        f"{iters} CG iterations {ms_s:.1f} ms ({gbs:.0f} GB/s algorithmic), residual {res:.2e}")
+    return {"B": B, "P": P, "jacobian_ms": ms_j, "jacobian_rows_per_s": 2 * B / (ms_j / 1e3), "cg_iters": iters,
+            "cg_ms": ms_s, "cg_GB/s": gbs, "cg_frac_of_8TB/s": gbs / 8000.0, "residual": res, "lambda": 1e-3}
 
 
 def bench_lattice2d(ctx, synth, B=16384):

@@ -275,6 +275,28 @@ int32_t tdo_sgd_step(int64_t P, float *params, const double *grad, double lr, hi
 int32_t tdo_adam_step(int64_t P, float *params, const double *grad, double *m, double *v, int64_t t,
                       double lr, double beta1, double beta2, double eps, hipStream_t stream);
 
+/* Per-sample log-derivatives O_k(x_b) = d log rho(x_b) / d theta_k (App. C,
+ * metric tensor of stochastic reconfiguration): jac, device double
+ * [B][2][P], row (b, 0) the real and row (b, 1) the imaginary part.  One
+ * backward pass per row through the kernels of tdo_log_rho_vjp, on weights
+ * packed once. */
+int32_t tdo_log_rho_jacobian(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                             const uint64_t *cfg, int64_t B, tdo_prec_t prec, double *jac,
+                             hipStream_t stream);
+
+/* Stochastic reconfiguration (App. C, metric tensor and hybrid update): x =
+ * (S + lambda I)^-1 g with S = Re sum_b w_b conj(dO(x_b)) dO(x_b)^T,
+ * dO = O - sum_b w_b O(x_b), weights normalised to sum 1 (weights: device
+ * double [B], or NULL for equal weights).  jac: device double [B][2][P] from
+ * tdo_log_rho_jacobian, centred and scaled in place (rows sqrt(w_b) dO).
+ * grad: device double [P]; x: device double [P], written.  Conjugate gradients
+ * from x = 0 for exactly `iters` iterations (S is applied as J^T (J p), never
+ * formed); info: device double [2] or NULL: the relative residual |r|/|g| of
+ * the recurrence and |g|.  lambda > 0. */
+int32_t tdo_sr_solve(tdo_ctx_t *ctx, double *jac, int64_t B, int64_t P, const double *weights,
+                     const double *grad, double lambda, int32_t iters, double *x, double *info,
+                     hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

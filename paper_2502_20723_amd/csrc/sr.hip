@@ -1,0 +1,190 @@
+// Stochastic reconfiguration (App. C, metric tensor and hybrid update):
+// solve (S + lambda I) x = g with
+//   S_kl = Re sum_b w_b conj(dO_k(x_b)) dO_l(x_b),  dO = O - sum_b w_b O(x_b),
+// O_k(x) = d log rho(x) / d theta_k, w normalised to sum 1, for the real
+// parameters theta.  With J the 2B x P matrix of rows sqrt(w_b) dRe O(x_b) and
+// sqrt(w_b) dIm O(x_b), S = J^T J, so S is never formed: conjugate gradients
+// on (J^T J + lambda I) x = g take two passes over J per iteration (rows
+// u = J p, then columns J^T u).
+//
+// The Jacobian comes from tdo_log_rho_jacobian; this call centres and scales
+// it in place.  Dot products are single-workgroup FP64 sums in a fixed order
+// and CG's scalars stay on the device, so the iteration count is fixed by the
+// caller and the result does not depend on scheduling.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+
+namespace tdo {
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ double block_reduce(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int h = kT / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace
+
+// sc[0] = sum of the weights (B when w is NULL).
+__global__ void __launch_bounds__(kT) k_sr_wsum(const double* __restrict__ w, int64_t B, double* __restrict__ sc) {
+  __shared__ double red[kT];
+  double a = 0.0;
+  for (int64_t b = threadIdx.x; b < B; b += kT) a += w ? w[b] : 1.0;
+  a = block_reduce(a, red);
+  if (threadIdx.x == 0) sc[0] = a;
+}
+
+// Column k: subtract the weighted mean of each part and scale row b by sqrt(w_b / sum w).
+__global__ void k_sr_center(double* __restrict__ J, int64_t B, int64_t P, const double* __restrict__ w,
+                            const double* __restrict__ sc) {
+  const double inv = 1.0 / sc[0];
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
+    for (int part = 0; part < 2; ++part) {
+      double mean = 0.0;
+      for (int64_t b = 0; b < B; ++b) mean += (w ? w[b] : 1.0) * inv * J[(2 * b + part) * P + k];
+      for (int64_t b = 0; b < B; ++b) {
+        double* e = J + (2 * b + part) * P + k;
+        *e = sqrt((w ? w[b] : 1.0) * inv) * (*e - mean);
+      }
+    }
+  }
+}
+
+// u[r] = J[r] . p, one workgroup per row.
+__global__ void __launch_bounds__(kT) k_sr_rows(const double* __restrict__ J, int64_t R, int64_t P,
+                                                const double* __restrict__ p, double* __restrict__ u) {
+  __shared__ double red[kT];
+  for (int64_t r = blockIdx.x; r < R; r += gridDim.x) {
+    const double* row = J + r * P;
+    double a = 0.0;
+    for (int64_t k = threadIdx.x; k < P; k += kT) a += row[k] * p[k];
+    a = block_reduce(a, red);
+    if (threadIdx.x == 0) u[r] = a;
+  }
+}
+
+// Ap[k] = sum_r J[r][k] u[r] + lambda p[k], one thread per column.
+__global__ void k_sr_cols(const double* __restrict__ J, int64_t R, int64_t P, const double* __restrict__ u,
+                          const double* __restrict__ p, double lambda, double* __restrict__ Ap) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
+    double a = 0.0;
+    for (int64_t r = 0; r < R; ++r) a += J[r * P + k] * u[r];
+    Ap[k] = a + lambda * p[k];
+  }
+}
+
+// out[0] = a . b in a fixed order (one workgroup).
+__global__ void __launch_bounds__(kT) k_sr_dot(const double* __restrict__ a, const double* __restrict__ b,
+                                               int64_t P, double* __restrict__ out) {
+  __shared__ double red[kT];
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < P; k += kT) s += a[k] * b[k];
+  s = block_reduce(s, red);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+// x <- 0, r <- g, p <- g.
+__global__ void k_sr_init(const double* __restrict__ g, int64_t P, double* __restrict__ x, double* __restrict__ r,
+                          double* __restrict__ p) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
+    x[k] = 0.0;
+    r[k] = g[k];
+    p[k] = g[k];
+  }
+}
+
+// alpha = rs / (p . Ap) (0 when p . Ap = 0); x += alpha p; r -= alpha Ap.
+__global__ void k_sr_step(int64_t P, const double* __restrict__ sc, const double* __restrict__ p,
+                          const double* __restrict__ Ap, double* __restrict__ x, double* __restrict__ r) {
+  const double pAp = sc[2], rs = sc[1];
+  const double alpha = pAp != 0.0 ? rs / pAp : 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
+    x[k] += alpha * p[k];
+    r[k] -= alpha * Ap[k];
+  }
+}
+
+// beta = rs_new / rs (0 when rs = 0); p = r + beta p.
+__global__ void k_sr_dir(int64_t P, const double* __restrict__ sc, const double* __restrict__ r,
+                         double* __restrict__ p) {
+  const double rs = sc[1], rn = sc[3];
+  const double beta = rs != 0.0 ? rn / rs : 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = r[k] + beta * p[k];
+}
+
+// rs <- rs_new.
+__global__ void k_sr_roll(double* __restrict__ sc) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[1] = sc[3];
+}
+
+// info[0] = |r| / |g| from the recurrence, info[1] = |g|.
+__global__ void k_sr_info(const double* __restrict__ sc, double* __restrict__ info) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double gn = sqrt(sc[4]);
+    info[0] = gn > 0.0 ? sqrt(sc[1]) / gn : 0.0;
+    info[1] = gn;
+  }
+}
+
+}  // namespace tdo
+
+using namespace tdo;
+
+extern "C" int32_t tdo_sr_solve(tdo_ctx_t* ctx, double* jac, int64_t B, int64_t P, const double* weights,
+                                const double* grad, double lambda, int32_t iters, double* x, double* info,
+                                hipStream_t stream) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  TDO_CHECK(B >= 1 && P >= 1, TDO_EINVAL, "B=%lld, P=%lld: both must be >= 1", (long long)B, (long long)P);
+  TDO_CHECK(lambda > 0.0 && std::isfinite(lambda), TDO_EINVAL, "diagonal shift lambda=%g must be positive", lambda);
+  TDO_CHECK(iters >= 0, TDO_EINVAL, "iters=%d < 0", iters);
+  TDO_CHECK(jac && grad && x, TDO_EINVAL, "NULL buffer");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  Context& c = ctx->c;
+  Arena ar;
+  const size_t or_ = ar.take<double>((size_t)P), op = ar.take<double>((size_t)P), oap = ar.take<double>((size_t)P);
+  const size_t ou = ar.take<double>(2 * (size_t)B), osc = ar.take<double>(8);
+  TDO_TRY(ensure_workspace(&c, ar.used));
+  double* r = at<double>(c.ws, or_);
+  double* p = at<double>(c.ws, op);
+  double* Ap = at<double>(c.ws, oap);
+  double* u = at<double>(c.ws, ou);
+  double* sc = at<double>(c.ws, osc);  // [0] sum w, [1] rs, [2] p.Ap, [3] rs_new, [4] g.g
+  const int64_t R = 2 * B;
+  const unsigned gp = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P, 256), 4096));
+  const unsigned gr = (unsigned)std::min<int64_t>(R, 8192);
+  hipLaunchKernelGGL(k_sr_wsum, dim3(1), dim3(kT), 0, stream, weights, B, sc);
+  hipLaunchKernelGGL(k_sr_center, dim3(gp), dim3(256), 0, stream, jac, B, P, weights, sc);
+  hipLaunchKernelGGL(k_sr_init, dim3(gp), dim3(256), 0, stream, grad, P, x, r, p);
+  hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(kT), 0, stream, grad, grad, P, sc + 1);
+  hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(kT), 0, stream, grad, grad, P, sc + 4);
+  TDO_HIP(hipGetLastError());
+  for (int32_t it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(k_sr_rows, dim3(gr), dim3(kT), 0, stream, jac, R, P, p, u);
+    hipLaunchKernelGGL(k_sr_cols, dim3(gp), dim3(256), 0, stream, jac, R, P, u, p, lambda, Ap);
+    hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(kT), 0, stream, p, Ap, P, sc + 2);
+    hipLaunchKernelGGL(k_sr_step, dim3(gp), dim3(256), 0, stream, P, sc, p, Ap, x, r);
+    hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(kT), 0, stream, r, r, P, sc + 3);
+    hipLaunchKernelGGL(k_sr_dir, dim3(gp), dim3(256), 0, stream, P, sc, r, p);
+    hipLaunchKernelGGL(k_sr_roll, dim3(1), dim3(64), 0, stream, sc);
+    TDO_HIP(hipGetLastError());
+  }
+  if (info) {
+    hipLaunchKernelGGL(k_sr_info, dim3(1), dim3(64), 0, stream, sc, info);
+    TDO_HIP(hipGetLastError());
+  }
+  return TDO_OK;
+}

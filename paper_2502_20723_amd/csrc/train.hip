@@ -49,6 +49,12 @@ __device__ __forceinline__ void lse_split(float gre, float gim, const float* __r
 }
 
 // VJP seeds: seed (dRe, dIm) on log rho -> g = dRe - i dIm.
+// Seeds of one configuration for d(s_re Re log rho + s_im Im log rho) (the
+// Jacobian rows).
+__global__ void k_seeds_const(float s_re, float s_im, const float* __restrict__ z, float* __restrict__ dF) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) lse_split(s_re, -s_im, z, dF);
+}
+
 __global__ void k_seeds_vjp(const float* __restrict__ seed, const float* __restrict__ z, int64_t E, float* __restrict__ dF) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x)
     lse_split(seed[2 * e], -seed[2 * e + 1], z + 4 * e, dF + 4 * e);
@@ -295,6 +301,49 @@ extern "C" int32_t tdo_log_rho_vjp(tdo_ctx_t* ctx, const tdo_arch_t* arch, const
     TDO_TRY(run_backward(np, w, bb, params, ec, E, nullptr, sv, at<float>(ws, t.dF), grad, stream));
   }
   TDO_TRY(finish_backward(np, bb, params, grad, stream));
+  return TDO_OK;
+}
+
+// Per-sample log-derivatives, one VJP per (configuration, part) on weights packed
+// once: the same launch sequence as tdo_log_rho_vjp with one configuration.
+extern "C" int32_t tdo_log_rho_jacobian(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params, int32_t n,
+                                        const uint64_t* cfg, int64_t B, tdo_prec_t prec, double* jac,
+                                        hipStream_t stream) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  TDO_CHECK(prec == TDO_FP32 || prec == TDO_BF16, TDO_EINVAL, "unknown precision %d", (int)prec);
+  NetPlan np;
+  TDO_TRY(net_plan(&ctx->c, arch, n, prec == TDO_BF16, &np));
+  TDO_CHECK(B >= 0, TDO_EINVAL, "B=%lld < 0", (long long)B);
+  if (B == 0) return TDO_OK;
+  TDO_CHECK(params && cfg && jac, TDO_EINVAL, "NULL buffer");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  Context& c = ctx->c;
+  TrainWs t;
+  TDO_TRY(plan_train(c, np, 1, 1, &t));
+  void* ws = c.ws;
+  NetWeights w = weights_at(ws, t.woff);
+  TDO_TRY(pack_weights(np, params, &w, stream));
+  TDO_TRY(launch_pack_backward(np.pp, params, np.bf16, at<char>(ws, t.wback), stream));
+  BwdBufs bb{at<char>(ws, t.wback), at<float>(ws, t.xa), at<float>(ws, t.xb), at<float>(ws, t.partial), c.num_cus,
+             at<double>(ws, t.mlp_acc), at<double>(ws, t.attn_acc), at<double>(ws, t.dT_acc)};
+  Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes,
+           t.lse_layer ? at<float>(ws, t.slse) : nullptr, t.lse_layer};
+  const int64_t P = np.pp.nparams;
+  for (int64_t b = 0; b < B; ++b) {
+    for (int part = 0; part < 2; ++part) {
+      double* row = jac + (2 * b + part) * P;
+      TDO_TRY(fill(row, P, 0.0, stream));
+      TDO_TRY(fill(at<double>(ws, t.dT_acc), 64LL * np.D, 0.0, stream));
+      TDO_TRY(run_forward(np, w, cfg + 2 * b, 1, nullptr, at<float>(ws, t.xa), at<float>(ws, t.xb), &sv,
+                          at<float>(ws, t.z), stream));
+      hipLaunchKernelGGL(k_seeds_const, dim3(1), dim3(64), 0, stream, part == 0 ? 1.f : 0.f, part == 1 ? 1.f : 0.f,
+                         at<float>(ws, t.z), at<float>(ws, t.dF));
+      TDO_HIP(hipGetLastError());
+      TDO_TRY(run_backward(np, w, bb, params, cfg + 2 * b, 1, nullptr, sv, at<float>(ws, t.dF), row, stream));
+      TDO_TRY(finish_backward(np, bb, params, row, stream));
+    }
+  }
   return TDO_OK;
 }
 

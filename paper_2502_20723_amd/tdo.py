@@ -22,7 +22,8 @@ PREC = {"fp32": TDO_FP32, "bf16": TDO_BF16}
 EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_error", "tdo_profile",
            "tdo_profile_read", "tdo_connected", "tdo_local_lindbladian", "tdo_log_rho", "tdo_log_rho_vjp",
            "tdo_loss_grad", "tdo_loss_grad_batched", "tdo_sample", "tdo_sample_diag", "tdo_observables",
-           "tdo_purity", "tdo_lr_schedule", "tdo_sgd_step", "tdo_adam_step")
+           "tdo_purity", "tdo_lr_schedule", "tdo_sgd_step", "tdo_adam_step", "tdo_log_rho_jacobian",
+           "tdo_sr_solve")
 
 
 class ArchT(ctypes.Structure):
@@ -77,6 +78,8 @@ def lib() -> ctypes.CDLL:
         L.tdo_lr_schedule.argtypes = [i64, dbl, i64, i64, dbl]
         L.tdo_sgd_step.argtypes = [i64, vp, vp, dbl, vp]
         L.tdo_adam_step.argtypes = [i64, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, vp]
+        L.tdo_log_rho_jacobian.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp]
+        L.tdo_sr_solve.argtypes = [vp, vp, i64, i64, vp, vp, dbl, i32, vp, vp, vp]
         for name in EXPORTS:
             if name not in ("tdo_last_error", "tdo_num_params", "tdo_ctx_create", "tdo_ctx_destroy",
                             "tdo_lr_schedule"):
@@ -286,6 +289,30 @@ class Ctx:
         _check(lib().tdo_sample(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, C, _ptr(state), _ptr(state_lr),
                                 seed, ctypes.byref(ctr), sweeps, p_pair, PREC[prec], _ptr(samples), _stream()))
         return samples, int(ctr.value)
+
+    def jacobian(self, arch: dict, params, n: int, cfg, prec="fp32"):
+        """O(x_b) = d log rho(x_b)/d theta as float64 [B, 2, P] (real, imaginary rows)."""
+        B, P = cfg.shape[0], num_params(arch)
+        _dev(params, torch.float32, (P,), "params")
+        _dev(cfg, torch.uint64, (B, 2), "cfg")
+        jac = torch.empty((B, 2, P), dtype=torch.float64, device=cfg.device)
+        _check(lib().tdo_log_rho_jacobian(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(cfg), B,
+                                          PREC[prec], _ptr(jac), _stream()))
+        return jac
+
+    def sr_solve(self, jac, grad, lam: float, iters: int, weights=None):
+        """x = (S + lam I)^-1 grad by conjugate gradients; jac ([B, 2, P] float64) is
+        centred and scaled in place.  Returns (x, info [rel. residual, |g|])."""
+        B, _, P = jac.shape
+        _dev(jac, torch.float64, (B, 2, P), "jac")
+        _dev(grad, torch.float64, (P,), "grad")
+        if weights is not None:
+            _dev(weights, torch.float64, (B,), "weights")
+        x = torch.empty((P,), dtype=torch.float64, device=jac.device)
+        info = torch.empty((2,), dtype=torch.float64, device=jac.device)
+        _check(lib().tdo_sr_solve(self.h, _ptr(jac), B, P, _ptr(weights), _ptr(grad), lam, iters, _ptr(x),
+                                  _ptr(info), _stream()))
+        return x, info
 
     def sample_diag(self, arch: dict, params, n: int, state, state_lr, seed: int, counter: int, sweeps: int,
                     prec="fp32"):
