@@ -5,11 +5,11 @@
 // parameters theta.  With J the 2B x P matrix of rows sqrt(w_b) dRe O(x_b) and
 // sqrt(w_b) dIm O(x_b), S = J^T J, so S is never formed: conjugate gradients
 // on (J^T J + lambda I) x = g take two passes over J per iteration (rows
-// u = J p, then columns J^T u).
+// u = J p in segments, then columns J^T u).
 //
 // The Jacobian comes from tdo_log_rho_jacobian; this call centres and scales
-// it in place.  Dot products are single-workgroup FP64 sums in a fixed order
-// and CG's scalars stay on the device, so the iteration count is fixed by the
+// it in place.  Dot products are two-stage FP64 sums in a fixed order (slices,
+// then one workgroup over the slices) and CG's scalars stay on the device, so the iteration count is fixed by the
 // caller and the result does not depend on scheduling.
 #include <algorithm>
 #include <cmath>
@@ -62,35 +62,58 @@ __global__ void k_sr_center(double* __restrict__ J, int64_t B, int64_t P, const 
   }
 }
 
-// u[r] = J[r] . p, one workgroup per row.
+// Partial row dots: workgroup (r, s) forms J[r] . p over segment s of kSeg equal
+// segments, into up[r][s] (summed in segment order by the column pass).
+constexpr int kSeg = 8;
 __global__ void __launch_bounds__(kT) k_sr_rows(const double* __restrict__ J, int64_t R, int64_t P,
-                                                const double* __restrict__ p, double* __restrict__ u) {
+                                                const double* __restrict__ p, double* __restrict__ up) {
   __shared__ double red[kT];
-  for (int64_t r = blockIdx.x; r < R; r += gridDim.x) {
+  const int64_t seg = (P + kSeg - 1) / kSeg;
+  for (int64_t rs = blockIdx.x; rs < R * kSeg; rs += gridDim.x) {
+    const int64_t r = rs / kSeg, s = rs % kSeg;
     const double* row = J + r * P;
+    const int64_t k1 = std::min<int64_t>(P, (s + 1) * seg);
     double a = 0.0;
-    for (int64_t k = threadIdx.x; k < P; k += kT) a += row[k] * p[k];
+    for (int64_t k = s * seg + threadIdx.x; k < k1; k += kT) a += row[k] * p[k];
     a = block_reduce(a, red);
-    if (threadIdx.x == 0) u[r] = a;
+    if (threadIdx.x == 0) up[rs] = a;
   }
 }
 
 // Ap[k] = sum_r J[r][k] u[r] + lambda p[k], one thread per column.
-__global__ void k_sr_cols(const double* __restrict__ J, int64_t R, int64_t P, const double* __restrict__ u,
+// (u[r] = sum over s of up[r][s], in segment order; every thread forms the same value.)
+__global__ void k_sr_cols(const double* __restrict__ J, int64_t R, int64_t P, const double* __restrict__ up,
                           const double* __restrict__ p, double lambda, double* __restrict__ Ap) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
     double a = 0.0;
-    for (int64_t r = 0; r < R; ++r) a += J[r * P + k] * u[r];
+    for (int64_t r = 0; r < R; ++r) {
+      double u = 0.0;
+#pragma unroll
+      for (int s = 0; s < kSeg; ++s) u += up[r * kSeg + s];
+      a += J[r * P + k] * u;
+    }
     Ap[k] = a + lambda * p[k];
   }
 }
 
-// out[0] = a . b in a fixed order (one workgroup).
+// a . b in a fixed order: kDotParts workgroups sum contiguous slices into part[],
+// then one workgroup sums the parts (k_sr_dot_fin).
+constexpr int kDotParts = 256;
 __global__ void __launch_bounds__(kT) k_sr_dot(const double* __restrict__ a, const double* __restrict__ b,
-                                               int64_t P, double* __restrict__ out) {
+                                               int64_t P, double* __restrict__ part) {
+  __shared__ double red[kT];
+  const int64_t slice = (P + kDotParts - 1) / kDotParts;
+  const int64_t k0 = blockIdx.x * slice, k1 = std::min<int64_t>(P, k0 + slice);
+  double s = 0.0;
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += kT) s += a[k] * b[k];
+  s = block_reduce(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kT) k_sr_dot_fin(const double* __restrict__ part, double* __restrict__ out) {
   __shared__ double red[kT];
   double s = 0.0;
-  for (int64_t k = threadIdx.x; k < P; k += kT) s += a[k] * b[k];
+  for (int i = threadIdx.x; i < kDotParts; i += kT) s += part[i];
   s = block_reduce(s, red);
   if (threadIdx.x == 0) out[0] = s;
 }
@@ -156,28 +179,36 @@ extern "C" int32_t tdo_sr_solve(tdo_ctx_t* ctx, double* jac, int64_t B, int64_t 
   Context& c = ctx->c;
   Arena ar;
   const size_t or_ = ar.take<double>((size_t)P), op = ar.take<double>((size_t)P), oap = ar.take<double>((size_t)P);
-  const size_t ou = ar.take<double>(2 * (size_t)B), osc = ar.take<double>(8);
+  const size_t ou = ar.take<double>(2 * (size_t)B * kSeg), osc = ar.take<double>(8);
+  const size_t opart = ar.take<double>(kDotParts);
   TDO_TRY(ensure_workspace(&c, ar.used));
   double* r = at<double>(c.ws, or_);
   double* p = at<double>(c.ws, op);
   double* Ap = at<double>(c.ws, oap);
   double* u = at<double>(c.ws, ou);
   double* sc = at<double>(c.ws, osc);  // [0] sum w, [1] rs, [2] p.Ap, [3] rs_new, [4] g.g
+  double* part = at<double>(c.ws, opart);
+  auto dot = [&](const double* a, const double* b, double* out) -> int32_t {
+    hipLaunchKernelGGL(k_sr_dot, dim3(kDotParts), dim3(kT), 0, stream, a, b, P, part);
+    hipLaunchKernelGGL(k_sr_dot_fin, dim3(1), dim3(kT), 0, stream, part, out);
+    TDO_HIP(hipGetLastError());
+    return TDO_OK;
+  };
   const int64_t R = 2 * B;
   const unsigned gp = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P, 256), 4096));
-  const unsigned gr = (unsigned)std::min<int64_t>(R, 8192);
+  const unsigned gr = (unsigned)std::min<int64_t>(R * kSeg, 16384);
   hipLaunchKernelGGL(k_sr_wsum, dim3(1), dim3(kT), 0, stream, weights, B, sc);
   hipLaunchKernelGGL(k_sr_center, dim3(gp), dim3(256), 0, stream, jac, B, P, weights, sc);
   hipLaunchKernelGGL(k_sr_init, dim3(gp), dim3(256), 0, stream, grad, P, x, r, p);
-  hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(kT), 0, stream, grad, grad, P, sc + 1);
-  hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(kT), 0, stream, grad, grad, P, sc + 4);
   TDO_HIP(hipGetLastError());
+  TDO_TRY(dot(grad, grad, sc + 1));
+  TDO_TRY(dot(grad, grad, sc + 4));
   for (int32_t it = 0; it < iters; ++it) {
     hipLaunchKernelGGL(k_sr_rows, dim3(gr), dim3(kT), 0, stream, jac, R, P, p, u);
     hipLaunchKernelGGL(k_sr_cols, dim3(gp), dim3(256), 0, stream, jac, R, P, u, p, lambda, Ap);
-    hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(kT), 0, stream, p, Ap, P, sc + 2);
+    TDO_TRY(dot(p, Ap, sc + 2));
     hipLaunchKernelGGL(k_sr_step, dim3(gp), dim3(256), 0, stream, P, sc, p, Ap, x, r);
-    hipLaunchKernelGGL(k_sr_dot, dim3(1), dim3(kT), 0, stream, r, r, P, sc + 3);
+    TDO_TRY(dot(r, r, sc + 3));
     hipLaunchKernelGGL(k_sr_dir, dim3(gp), dim3(256), 0, stream, P, sc, r, p);
     hipLaunchKernelGGL(k_sr_roll, dim3(1), dim3(64), 0, stream, sc);
     TDO_HIP(hipGetLastError());
