@@ -304,8 +304,9 @@ extern "C" int32_t tdo_log_rho_vjp(tdo_ctx_t* ctx, const tdo_arch_t* arch, const
   return TDO_OK;
 }
 
-// Per-sample log-derivatives, one VJP per (configuration, part) on weights packed
-// once: the same launch sequence as tdo_log_rho_vjp with one configuration.
+// Per-sample log-derivatives: per configuration one forward, then one backward
+// per part (Re, Im) with the launch sequence of tdo_log_rho_vjp on one
+// configuration, on weights packed once.
 extern "C" int32_t tdo_log_rho_jacobian(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params, int32_t n,
                                         const uint64_t* cfg, int64_t B, tdo_prec_t prec, double* jac,
                                         hipStream_t stream) {
@@ -331,12 +332,13 @@ extern "C" int32_t tdo_log_rho_jacobian(tdo_ctx_t* ctx, const tdo_arch_t* arch, 
            t.lse_layer ? at<float>(ws, t.slse) : nullptr, t.lse_layer};
   const int64_t P = np.pp.nparams;
   for (int64_t b = 0; b < B; ++b) {
+    // one forward per configuration: the backward only reads the saved activations and z
+    TDO_TRY(run_forward(np, w, cfg + 2 * b, 1, nullptr, at<float>(ws, t.xa), at<float>(ws, t.xb), &sv,
+                        at<float>(ws, t.z), stream));
     for (int part = 0; part < 2; ++part) {
       double* row = jac + (2 * b + part) * P;
       TDO_TRY(fill(row, P, 0.0, stream));
       TDO_TRY(fill(at<double>(ws, t.dT_acc), 64LL * np.D, 0.0, stream));
-      TDO_TRY(run_forward(np, w, cfg + 2 * b, 1, nullptr, at<float>(ws, t.xa), at<float>(ws, t.xb), &sv,
-                          at<float>(ws, t.z), stream));
       hipLaunchKernelGGL(k_seeds_const, dim3(1), dim3(64), 0, stream, part == 0 ? 1.f : 0.f, part == 1 ? 1.f : 0.f,
                          at<float>(ws, t.z), at<float>(ws, t.dF));
       TDO_HIP(hipGetLastError());
