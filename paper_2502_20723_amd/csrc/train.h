@@ -48,6 +48,7 @@ struct TrainWs {
   size_t cnt, off, etot, ecfg, ecoef, eowner, lr, z, dF, xa, xb, sx, smid, slast, slse;
   int64_t chunk, emax, nblk;
   size_t layer_bytes, lse_layer;
+  size_t total;  // bytes of the whole plan
 };
 
 struct ModelDev;

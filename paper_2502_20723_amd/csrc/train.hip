@@ -260,6 +260,7 @@ int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, T
   t->slast = ar.take<char>(t->layer_bytes);
   t->lse_layer = keep_lse ? (size_t)t->nblk * 32 * (np.D / np.DH) : 0;
   t->slse = ar.take<float>(t->lse_layer * pp.layers + 64);
+  t->total = ar.used;
   TDO_TRY(ensure_workspace(const_cast<Context*>(&c), ar.used));
   return TDO_OK;
 }
@@ -322,31 +323,72 @@ extern "C" int32_t tdo_log_rho_jacobian(tdo_ctx_t* ctx, const tdo_arch_t* arch, 
   Context& c = ctx->c;
   TrainWs t;
   TDO_TRY(plan_train(c, np, 1, 1, &t));
-  void* ws = c.ws;
-  NetWeights w = weights_at(ws, t.woff);
+  // kLanes independent copies of the one-configuration scratch, each driven on its
+  // own stream (a single configuration occupies a few workgroups); the packed
+  // weights of copy 0 are shared
+  constexpr int kLanes = 4;
+  const int lanes = (int)std::min<int64_t>(kLanes, B);
+  const size_t stride = (t.total + 4095) & ~size_t(4095);
+  TDO_TRY(ensure_workspace(&c, stride * lanes));
+  char* ws0 = static_cast<char*>(c.ws);
+  NetWeights w = weights_at(ws0, t.woff);
   TDO_TRY(pack_weights(np, params, &w, stream));
-  TDO_TRY(launch_pack_backward(np.pp, params, np.bf16, at<char>(ws, t.wback), stream));
-  BwdBufs bb{at<char>(ws, t.wback), at<float>(ws, t.xa), at<float>(ws, t.xb), at<float>(ws, t.partial), c.num_cus,
-             at<double>(ws, t.mlp_acc), at<double>(ws, t.attn_acc), at<double>(ws, t.dT_acc)};
-  Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes,
-           t.lse_layer ? at<float>(ws, t.slse) : nullptr, t.lse_layer};
+  TDO_TRY(launch_pack_backward(np.pp, params, np.bf16, at<char>(ws0, t.wback), stream));
   const int64_t P = np.pp.nparams;
-  for (int64_t b = 0; b < B; ++b) {
+  hipStream_t st[kLanes];
+  hipEvent_t ev[kLanes + 1];
+  int made_st = 0, made_ev = 0;
+  int32_t rc = TDO_OK;
+  auto cleanup = [&]() {
+    for (int i = 0; i < made_st; ++i) (void)hipStreamDestroy(st[i]);
+    for (int i = 0; i < made_ev; ++i) (void)hipEventDestroy(ev[i]);
+  };
+#define JAC_HIP(call)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      rc = set_error(TDO_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));                \
+      cleanup();                                                                              \
+      return rc;                                                                              \
+    }                                                                                         \
+  } while (0)
+  for (int i = 0; i <= lanes; ++i, ++made_ev) JAC_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+  for (int i = 0; i < lanes; ++i, ++made_st) JAC_HIP(hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking));
+  JAC_HIP(hipEventRecord(ev[lanes], stream));  // packed weights ready
+  for (int i = 0; i < lanes; ++i) JAC_HIP(hipStreamWaitEvent(st[i], ev[lanes], 0));
+  for (int64_t b = 0; b < B && rc == TDO_OK; ++b) {
+    const int lane = (int)(b % lanes);
+    hipStream_t s = st[lane];
+    char* ws = ws0 + stride * lane;
+    BwdBufs bb{at<char>(ws0, t.wback), at<float>(ws, t.xa), at<float>(ws, t.xb), at<float>(ws, t.partial), c.num_cus,
+               at<double>(ws, t.mlp_acc), at<double>(ws, t.attn_acc), at<double>(ws, t.dT_acc)};
+    Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes,
+             t.lse_layer ? at<float>(ws, t.slse) : nullptr, t.lse_layer};
     // one forward per configuration: the backward only reads the saved activations and z
-    TDO_TRY(run_forward(np, w, cfg + 2 * b, 1, nullptr, at<float>(ws, t.xa), at<float>(ws, t.xb), &sv,
-                        at<float>(ws, t.z), stream));
-    for (int part = 0; part < 2; ++part) {
+    rc = run_forward(np, w, cfg + 2 * b, 1, nullptr, at<float>(ws, t.xa), at<float>(ws, t.xb), &sv,
+                     at<float>(ws, t.z), s);
+    for (int part = 0; part < 2 && rc == TDO_OK; ++part) {
       double* row = jac + (2 * b + part) * P;
-      TDO_TRY(fill(row, P, 0.0, stream));
-      TDO_TRY(fill(at<double>(ws, t.dT_acc), 64LL * np.D, 0.0, stream));
-      hipLaunchKernelGGL(k_seeds_const, dim3(1), dim3(64), 0, stream, part == 0 ? 1.f : 0.f, part == 1 ? 1.f : 0.f,
-                         at<float>(ws, t.z), at<float>(ws, t.dF));
-      TDO_HIP(hipGetLastError());
-      TDO_TRY(run_backward(np, w, bb, params, cfg + 2 * b, 1, nullptr, sv, at<float>(ws, t.dF), row, stream));
-      TDO_TRY(finish_backward(np, bb, params, row, stream));
+      rc = fill(row, P, 0.0, s);
+      if (rc == TDO_OK) rc = fill(at<double>(ws, t.dT_acc), 64LL * np.D, 0.0, s);
+      if (rc == TDO_OK) {
+        hipLaunchKernelGGL(k_seeds_const, dim3(1), dim3(64), 0, s, part == 0 ? 1.f : 0.f, part == 1 ? 1.f : 0.f,
+                           at<float>(ws, t.z), at<float>(ws, t.dF));
+        if (hipGetLastError() != hipSuccess) rc = set_error(TDO_EHIP, "k_seeds_const launch failed");
+      }
+      if (rc == TDO_OK) rc = run_backward(np, w, bb, params, cfg + 2 * b, 1, nullptr, sv, at<float>(ws, t.dF), row, s);
+      if (rc == TDO_OK) rc = finish_backward(np, bb, params, row, s);
     }
   }
-  return TDO_OK;
+  // join: the caller's stream waits for every lane (also after an error, so that
+  // nothing still runs on the scratch when the call returns)
+  for (int i = 0; i < lanes; ++i) {
+    if (hipEventRecord(ev[i], st[i]) == hipSuccess) (void)hipStreamWaitEvent(stream, ev[i], 0);
+  }
+  for (int i = 0; i < lanes; ++i) (void)hipStreamSynchronize(st[i]);
+#undef JAC_HIP
+  cleanup();
+  return rc;
 }
 
 namespace tdo {
