@@ -277,9 +277,12 @@ int32_t tdo_adam_step(int64_t P, float *params, const double *grad, double *m, d
 
 /* Per-sample log-derivatives O_k(x_b) = d log rho(x_b) / d theta_k (App. C,
  * metric tensor of stochastic reconfiguration): jac, device double
- * [B][2][P], row (b, 0) the real and row (b, 1) the imaginary part.  One
- * backward pass per row through the kernels of tdo_log_rho_vjp, on weights
- * packed once. */
+ * [B][2][P], row (b, 0) the real and row (b, 1) the imaginary part.  Per
+ * configuration one forward and one backward per row through the kernels of
+ * tdo_log_rho_vjp, on weights packed once; configurations are spread over four
+ * internal streams (default priority) that wait for `stream` and that `stream`
+ * then waits for.  The call returns after the rows are written (it waits on
+ * the host). */
 int32_t tdo_log_rho_jacobian(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
                              const uint64_t *cfg, int64_t B, tdo_prec_t prec, double *jac,
                              hipStream_t stream);
