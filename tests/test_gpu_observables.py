@@ -329,3 +329,21 @@ def test_diag_full_size_sampled_chains(gpu):
                 state, lr = prop, lrp
         if not marginal:
             assert got[0, c] == state[0], c
+
+
+@pytest.mark.parametrize("n,B", [(3, 40), (64, 37), (40, 61)])
+def test_local_estimators_edge_lengths(gpu, n, B):
+    """The shortest chain, the longest (65 rows per sample, flips up to bit 63) and a
+    span length (two 32-row halves), FP32 and BF16, with the all-up and all-down
+    samples included."""
+    arch = SMALL
+    params = synth.params(arch, 90 + n, "mid")
+    a = alphas(n, B, 91 + n)
+    a[0] = 0
+    a[1] = np.uint64((1 << n) - 1) if n < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    ctx = gpu.Ctx(0)
+    ref = oracle_local(params, arch, n, a)
+    for prec in ("fp32", "bf16"):
+        lrd, local, _ = ctx.observables(arch, cuda(params), n, cuda(a), prec)
+        check_local(local.cpu().numpy(), lrd.cpu().numpy(), ref, prec, f"n={n} B={B}")
+    assert local[0, 2, 0].item() == 1.0 and local[1, 2, 0].item() == -1.0
