@@ -290,7 +290,7 @@ int32_t tdo_log_rho_jacobian(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float
 /* Stochastic reconfiguration (App. C, metric tensor and hybrid update): x =
  * (S + lambda I)^-1 g with S = Re sum_b w_b conj(dO(x_b)) dO(x_b)^T,
  * dO = O - sum_b w_b O(x_b), weights normalised to sum 1 (weights: device
- * double [B], or NULL for equal weights).  jac: device double [B][2][P] from
+ * double [B], non-negative with a positive sum, or NULL for equal weights).  jac: device double [B][2][P] from
  * tdo_log_rho_jacobian, centred and scaled in place (rows sqrt(w_b) dO).
  * grad: device double [P]; x: device double [P], written.  Conjugate gradients
  * from x = 0 for exactly `iters` iterations (S is applied as J^T (J p), never
