@@ -44,3 +44,24 @@ def test_invalid_arch_is_rejected():
         with pytest.raises(tdo.TdoError):
             tdo.num_params(a)
         assert tdo.lib().tdo_last_error().decode() != ""
+
+
+def test_new_entry_points_validate_before_any_device_call():
+    """Argument checks of the update, SR and observable calls happen on the host,
+    before anything is launched, so they run without a GPU."""
+    L = tdo.lib()
+    st = None
+    assert L.tdo_sgd_step(-1, None, None, 0.1, st) != 0
+    assert "P=" in L.tdo_last_error().decode()
+    assert L.tdo_sgd_step(0, None, None, 0.1, st) == 0                      # nothing to do
+    assert L.tdo_adam_step(4, None, None, None, None, 0, 1e-3, 0.9, 0.999, 1e-8, st) != 0
+    assert "t=0" in L.tdo_last_error().decode()
+    assert L.tdo_adam_step(4, None, None, None, None, 1, 1e-3, 1.0, 0.999, 1e-8, st) != 0
+    assert L.tdo_adam_step(4, None, None, None, None, 1, 1e-3, 0.9, 0.999, 0.0, st) != 0
+    assert L.tdo_sr_solve(None, None, 4, 10, None, None, 1e-3, 10, None, None, st) != 0
+    assert "ctx" in L.tdo_last_error().decode()
+    arch = tdo.arch_t(dict(d=16, heads=2, layers=1, mlp=64))
+    assert L.tdo_observables(None, ctypes.byref(arch), None, 4, None, 0, 0, None, None, None, st) != 0
+    assert L.tdo_purity(None, ctypes.byref(arch), None, 4, None, None, 1, 0, None, st) != 0
+    assert L.tdo_sample_diag(None, ctypes.byref(arch), None, 4, 1, None, None, 0, None, 1, 0, None, st) != 0
+    assert L.tdo_log_rho_jacobian(None, ctypes.byref(arch), None, 4, None, 1, 0, None, st) != 0
