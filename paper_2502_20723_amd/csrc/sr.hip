@@ -5,7 +5,7 @@
 // parameters theta.  With J the 2B x P matrix of rows sqrt(w_b) dRe O(x_b) and
 // sqrt(w_b) dIm O(x_b), S = J^T J, so S is never formed: conjugate gradients
 // on (J^T J + lambda I) x = g take two passes over J per iteration (rows
-// u = J p in segments, then columns J^T u).
+// u = J p in segments, the segment sums, then columns J^T u).
 //
 // The Jacobian comes from tdo_log_rho_jacobian; this call centres and scales
 // it in place.  Dot products are two-stage FP64 sums in a fixed order (slices,
@@ -80,19 +80,31 @@ __global__ void __launch_bounds__(kT) k_sr_rows(const double* __restrict__ J, in
   }
 }
 
-// Ap[k] = sum_r J[r][k] u[r] + lambda p[k], one thread per column.
-// (u[r] = sum over s of up[r][s], in segment order; every thread forms the same value.)
-__global__ void k_sr_cols(const double* __restrict__ J, int64_t R, int64_t P, const double* __restrict__ up,
+// u[r] = sum over s of up[r][s], in segment order.
+__global__ void k_sr_usum(const double* __restrict__ up, int64_t R, double* __restrict__ u) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+    double a = 0.0;
+#pragma unroll
+    for (int s = 0; s < kSeg; ++s) a += up[r * kSeg + s];
+    u[r] = a;
+  }
+}
+
+// Ap[k] = sum_r J[r][k] u[r] + lambda p[k], one thread per column; four
+// accumulators over r mod 4 (summed in that order) keep four loads in flight.
+__global__ void k_sr_cols(const double* __restrict__ J, int64_t R, int64_t P, const double* __restrict__ u,
                           const double* __restrict__ p, double lambda, double* __restrict__ Ap) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x) {
-    double a = 0.0;
-    for (int64_t r = 0; r < R; ++r) {
-      double u = 0.0;
-#pragma unroll
-      for (int s = 0; s < kSeg; ++s) u += up[r * kSeg + s];
-      a += J[r * P + k] * u;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t r = 0;
+    for (; r + 4 <= R; r += 4) {
+      a0 += J[r * P + k] * u[r];
+      a1 += J[(r + 1) * P + k] * u[r + 1];
+      a2 += J[(r + 2) * P + k] * u[r + 2];
+      a3 += J[(r + 3) * P + k] * u[r + 3];
     }
-    Ap[k] = a + lambda * p[k];
+    for (; r < R; ++r) a0 += J[r * P + k] * u[r];
+    Ap[k] = ((a0 + a1) + (a2 + a3)) + lambda * p[k];
   }
 }
 
@@ -179,12 +191,14 @@ extern "C" int32_t tdo_sr_solve(tdo_ctx_t* ctx, double* jac, int64_t B, int64_t 
   Context& c = ctx->c;
   Arena ar;
   const size_t or_ = ar.take<double>((size_t)P), op = ar.take<double>((size_t)P), oap = ar.take<double>((size_t)P);
-  const size_t ou = ar.take<double>(2 * (size_t)B * kSeg), osc = ar.take<double>(8);
+  const size_t oup = ar.take<double>(2 * (size_t)B * kSeg), ou = ar.take<double>(2 * (size_t)B);
+  const size_t osc = ar.take<double>(8);
   const size_t opart = ar.take<double>(kDotParts);
   TDO_TRY(ensure_workspace(&c, ar.used));
   double* r = at<double>(c.ws, or_);
   double* p = at<double>(c.ws, op);
   double* Ap = at<double>(c.ws, oap);
+  double* up = at<double>(c.ws, oup);
   double* u = at<double>(c.ws, ou);
   double* sc = at<double>(c.ws, osc);  // [0] sum w, [1] rs, [2] p.Ap, [3] rs_new, [4] g.g
   double* part = at<double>(c.ws, opart);
@@ -204,7 +218,9 @@ extern "C" int32_t tdo_sr_solve(tdo_ctx_t* ctx, double* jac, int64_t B, int64_t 
   TDO_TRY(dot(grad, grad, sc + 1));
   TDO_TRY(dot(grad, grad, sc + 4));
   for (int32_t it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL(k_sr_rows, dim3(gr), dim3(kT), 0, stream, jac, R, P, p, u);
+    hipLaunchKernelGGL(k_sr_rows, dim3(gr), dim3(kT), 0, stream, jac, R, P, p, up);
+    hipLaunchKernelGGL(k_sr_usum, dim3((unsigned)std::min<int64_t>(ceil_div(R, 256), 1024)), dim3(256), 0, stream,
+                       up, R, u);
     hipLaunchKernelGGL(k_sr_cols, dim3(gp), dim3(256), 0, stream, jac, R, P, u, p, lambda, Ap);
     TDO_TRY(dot(p, Ap, sc + 2));
     hipLaunchKernelGGL(k_sr_step, dim3(gp), dim3(256), 0, stream, P, sc, p, Ap, x, r);
