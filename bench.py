@@ -386,7 +386,8 @@ def bench_sampler(ctx, arch, params, n, synth):
 
 def bench_sr(ctx, arch, params, n, synth, B=256, iters=100):
     """Stochastic reconfiguration with the n = 32 network: the per-sample Jacobian of
-    B = 256 samples (2B backward passes, FP32), then 100 conjugate-gradient
+    B = 256 samples (2B backward passes, in BF16 and in FP32; the FP32 one feeds
+    the solve), then 100 conjugate-gradient
     iterations of (S + lambda I) x = g with S = J^T J applied as two passes over
     J (2B x P FP64).  Algorithmic HBM bytes per iteration: 2 x 2B x P x 8 (J read
     twice) plus the vectors."""
@@ -408,16 +409,22 @@ def bench_sr(ctx, arch, params, n, synth, B=256, iters=100):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1), out
 
+    ctx.jacobian(arch, params, n, cfg[:2], "bf16")
+    ms_jb, Jb = timed(lambda: ctx.jacobian(arch, params, n, cfg, "bf16"))
     ctx.jacobian(arch, params, n, cfg[:2], "fp32")
     ms_j, J = timed(lambda: ctx.jacobian(arch, params, n, cfg, "fp32"))
+    jb_err = float(((Jb - J).norm(dim=2) / J.norm(dim=(1, 2))[:, None]).max())
+    del Jb
     ctx.sr_solve(J.clone(), g, 1e-3, 2)
     ms_s, (x, info) = timed(lambda: ctx.sr_solve(J, g, 1e-3, iters))
     res = float(info.cpu()[0])
     it_bytes = 2 * (2 * B) * P * 8 + 6 * P * 8
     gbs = iters * it_bytes / (ms_s / 1e3) / 1e9
-    log(f"bench: SR n={n} B={B} P={P}: jacobian {ms_j:.1f} ms ({2 * B / (ms_j / 1e3):.0f} rows/s), "
+    log(f"bench: SR n={n} B={B} P={P}: jacobian {ms_j:.1f} ms ({2 * B / (ms_j / 1e3):.0f} rows/s; bf16 "
+        f"{ms_jb:.1f} ms, rows within {jb_err:.1e} of fp32), "
         f"{iters} CG iterations {ms_s:.1f} ms ({gbs:.0f} GB/s algorithmic), residual {res:.2e}")
-    return {"B": B, "P": P, "jacobian_ms": ms_j, "jacobian_rows_per_s": 2 * B / (ms_j / 1e3), "cg_iters": iters,
+    return {"B": B, "P": P, "jacobian_ms": ms_j, "jacobian_rows_per_s": 2 * B / (ms_j / 1e3),
+            "jacobian_bf16_ms": ms_jb, "jacobian_bf16_max_row_rel_diff_vs_fp32": jb_err, "cg_iters": iters,
             "cg_ms": ms_s, "cg_GB/s": gbs, "cg_frac_of_8TB/s": gbs / 8000.0, "residual": res, "lambda": 1e-3}
 
 

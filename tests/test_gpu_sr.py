@@ -39,6 +39,21 @@ def test_jacobian_matches_oracle(gpu, arch, n, B, scale):
     assert err.max() < 1e-4
 
 
+@pytest.mark.parametrize("n,B", [(7, 9), (32, 3)])
+def test_jacobian_bf16(gpu, n, B):
+    """The BF16 path's Jacobian: rows within 2e-2 of the oracle's (the stated BF16
+    bound on log rho), at mid-scale weights."""
+    arch = SMALL if n < 32 else synth.WORKLOADS["ising_n32"]["arch"]
+    params = synth.params(arch, 160 + n, "mid")
+    cfg = synth.configs(n, B, 161 + n)
+    ctx = gpu.Ctx(0)
+    J = ctx.jacobian(arch, cuda(params), n, cuda(cfg), "bf16").cpu().numpy()
+    R = osr.jacobian(params.astype(np.float64), oa.Arch(**arch), cfg, n)
+    err = np.linalg.norm(J - R, axis=2) / np.linalg.norm(R, axis=(1, 2))[:, None]
+    print(f"bf16 jacobian n={n} B={B}: max row rel L2 err {err.max():.3e}")
+    assert err.max() < 2e-2
+
+
 @pytest.mark.parametrize("weighted", [False, True])
 def test_sr_solve(gpu, weighted):
     arch, n, B = SMALL, 5, 24
