@@ -94,3 +94,36 @@ def test_exact_cost_2x3(gpu):
     err = abs(float(loss.cpu()[0]) - F) / abs(F)
     print(f"2 x 3 exact cost {F:.6e}, GPU rel err {err:.3e}")
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batched_mixes_lattices_and_chains(gpu, prec):
+    """tdo_loss_grad_batched over lattice and chain problems (eager, recorded and
+    replayed) equals separate tdo_loss_grad calls, and a lattice problem's loss
+    equals the oracle's."""
+    from tests.test_gpu_batched import REPEAT_TOL
+    arch = synth.WORKLOADS["batched_uneven"]["arch"]
+    models = [dict(kind=0, n=16, rows=2, V=1.3, g=0.9, gamma=1.0), dict(kind=0, n=12, V=0.8, g=1.2, gamma=1.0),
+              dict(kind=0, n=16, rows=4, V=2.0, g=1.0, gamma=1.0), dict(kind=1, n=10, Jx=0.9, Jy=1.1, Jz=1.2, gamma=1.0),
+              dict(kind=0, n=15, rows=3, V=0.7, g=1.4, gamma=0.9)]
+    params = [synth.params(arch, 300 + i, "mid") for i in range(len(models))]
+    cfgs = [synth.configs(m["n"], 48, 310 + i) for i, m in enumerate(models)]
+    ctx = gpu.Ctx(0)
+    pt, ct = [cuda(p) for p in params], [cuda(c) for c in cfgs]
+    ref = [ctx.loss_grad(arch, pt[i], models[i], ct[i], None, prec, "B") for i in range(len(models))]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        out = (torch.empty(len(models), dtype=torch.float64, device="cuda"),
+               [torch.empty(synth.num_params(arch), dtype=torch.float64, device="cuda") for _ in models])
+        for call in range(3):  # eager, recorded, replayed (same output buffers)
+            loss, grads = ctx.loss_grad_batched(arch, pt, models, ct, None, prec, "B", out=out)
+            s.synchronize()
+            for i in range(len(models)):
+                assert abs(float(loss[i]) - float(ref[i][0][0])) <= 1e-12 * abs(float(ref[i][0][0])), (call, i)
+                assert rel_l2(grads[i].cpu().numpy(), ref[i][1].cpu().numpy()) <= REPEAT_TOL[prec], (call, i)
+    torch.cuda.synchronize()
+    F = vmc.loss(params[2].astype(np.float64), oa.Arch(**arch), ol.Model(**models[2]), cfgs[2])[0]
+    err = abs(float(ref[2][0][0]) - F) / abs(F)
+    print(f"batched lattice {prec}: 4 x 4 loss rel err {err:.3e}")
+    assert err < LTOL[prec]
