@@ -231,7 +231,9 @@ int32_t tdo_sample_diag(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *par
  * (alpha, alpha) and (alpha, alpha with site i flipped).
  * log_rho_diag: device float [B][2], log rho(alpha, alpha) (imaginary part pi
  * where the diagonal is negative, real part -inf where it vanishes);
- * local: device float [B][3][2], (re, im) of A~ for x, y, z.  Where
+ * local: device float [B][3][2], (re, im) of A~ for x, y, z; local_site:
+ * device float [B][n][3][2] or NULL, the same for each single-site sigma^k_i
+ * (local is their average over i).  Where
  * rho(alpha, alpha) = 0 the ratios are read as 0 (sigma^z keeps its diagonal
  * value).  mean: device double [7] or NULL: mean[0..5] = sum s A~ / sum s over
  * the B samples for x, y, z as (re, im), with s = sign of rho(alpha, alpha),
@@ -240,7 +242,7 @@ int32_t tdo_sample_diag(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *par
  * non-finite means.  Sums are FP64 in a fixed order. */
 int32_t tdo_observables(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
                         const uint64_t *alpha, int64_t B, tdo_prec_t prec, float *log_rho_diag,
-                        float *local, double *mean, hipStream_t stream);
+                        float *local, float *local_site, double *mean, hipStream_t stream);
 
 /* Purity Tr(rho^2) / (Tr rho)^2 (Ising section) from P >= 1 pairs of
  * independent diagonal samples (alpha_p, beta_p) (device uint64 [P] each, e.g.

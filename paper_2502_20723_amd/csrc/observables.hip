@@ -77,9 +77,10 @@ __global__ void k_obs_rows(const uint64_t* __restrict__ alpha, int64_t S, int n,
 }
 
 // One thread per sample: the site averages (1/n) sum_i of the local estimators,
-// local[s] = (x re, x im, y re, y im, z re, z im), and log rho(alpha, alpha).
+// local[s] = (x re, x im, y re, y im, z re, z im), log rho(alpha, alpha), and
+// optionally the estimators of every site, site[s][i] in the same layout.
 __global__ void k_obs_local(const float* __restrict__ lr, const uint64_t* __restrict__ alpha, int64_t S, int n,
-                            float* __restrict__ lrd, float* __restrict__ local) {
+                            float* __restrict__ lrd, float* __restrict__ local, float* __restrict__ site) {
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x) {
     const float* l = lr + 2 * s * (n + 1);
     const float d_re = l[0], d_im = l[1];
@@ -91,15 +92,27 @@ __global__ void k_obs_local(const float* __restrict__ lr, const uint64_t* __rest
       const int si = ((a >> i) & 1ull) ? -1 : 1;
       z += si;
       const float o_re = l[2 + 2 * i], o_im = l[3 + 2 * i];
-      if (zero || o_re == -INFINITY) continue;
-      const double m = exp((double)o_re - (double)d_re);
-      double sn, cs;
-      sincos((double)o_im - (double)d_im, &sn, &cs);
-      const double rr = m * cs, ri = m * sn;
+      double rr = 0.0, ri = 0.0;
+      if (!zero && o_re != -INFINITY) {
+        const double m = exp((double)o_re - (double)d_re);
+        double sn, cs;
+        sincos((double)o_im - (double)d_im, &sn, &cs);
+        rr = m * cs;
+        ri = m * sn;
+      }
       xr += rr;
       xi += ri;
       yr -= si * ri;  // i s_i (rr + i ri)
       yi += si * rr;
+      if (site) {  // per site: (x, y, z) as (re, im)
+        float* q = site + (s * n + i) * 6;
+        q[0] = (float)rr;
+        q[1] = (float)ri;
+        q[2] = (float)(-si * ri);
+        q[3] = (float)(si * rr);
+        q[4] = (float)si;
+        q[5] = 0.f;
+      }
     }
     const double inv = 1.0 / n;
     lrd[2 * s] = d_re;
@@ -225,7 +238,7 @@ extern "C" {
 
 int32_t tdo_observables(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params, int32_t n,
                         const uint64_t* alpha, int64_t B, tdo_prec_t prec, float* log_rho_diag, float* local,
-                        double* mean, hipStream_t stream) {
+                        float* local_site, double* mean, hipStream_t stream) {
   clear_error();
   TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
   TDO_CHECK(prec == TDO_FP32 || prec == TDO_BF16, TDO_EINVAL, "unknown precision %d", (int)prec);
@@ -253,7 +266,7 @@ int32_t tdo_observables(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* par
                         at<float>(ws, rp.oz), stream));
     TDO_TRY(launch_symmetrise(nullptr, E, at<float>(ws, rp.oz), lr, stream));
     hipLaunchKernelGGL(k_obs_local, dim3(grid_for(S)), dim3(256), 0, stream, lr, alpha + s0, S, (int)n,
-                       log_rho_diag + 2 * s0, local + 6 * s0);
+                       log_rho_diag + 2 * s0, local + 6 * s0, local_site ? local_site + 6 * s0 * n : nullptr);
     TDO_HIP(hipGetLastError());
   }
   if (mean) {

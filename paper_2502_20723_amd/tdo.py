@@ -72,7 +72,7 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_uint64), i32, ctypes.c_float, i32, vp, vp]
         L.tdo_sample_diag.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, i64, vp, vp, ctypes.c_uint64,
                                       ctypes.POINTER(ctypes.c_uint64), i32, i32, vp, vp]
-        L.tdo_observables.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp, vp, vp]
+        L.tdo_observables.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp, vp, vp, vp]
         L.tdo_purity.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, vp, i64, i32, vp, vp]
         dbl = ctypes.c_double
         L.tdo_lr_schedule.argtypes = [i64, dbl, i64, i64, dbl]
@@ -327,18 +327,20 @@ class Ctx:
                                      _stream()))
         return samples, int(ctr.value)
 
-    def observables(self, arch: dict, params, n: int, alpha, prec="fp32", want_mean=True):
+    def observables(self, arch: dict, params, n: int, alpha, prec="fp32", want_mean=True, want_sites=False):
         """(log rho(alpha, alpha) [B, 2], local estimators [B, 3, 2] (x, y, z site averages),
-        sign-weighted means [7] float64 or None)."""
+        sign-weighted means [7] float64 or None); with want_sites, also the per-site
+        estimators [B, n, 3, 2] as a fourth element."""
         B = alpha.shape[0]
         _dev(params, torch.float32, (num_params(arch),), "params")
         _dev(alpha, torch.uint64, (B,), "alpha")
         lrd = torch.empty((B, 2), dtype=torch.float32, device=alpha.device)
         local = torch.empty((B, 3, 2), dtype=torch.float32, device=alpha.device)
         mean = torch.empty((7,), dtype=torch.float64, device=alpha.device) if want_mean else None
+        site = torch.empty((B, n, 3, 2), dtype=torch.float32, device=alpha.device) if want_sites else None
         _check(lib().tdo_observables(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(alpha), B,
-                                     PREC[prec], _ptr(lrd), _ptr(local), _ptr(mean), _stream()))
-        return lrd, local, mean
+                                     PREC[prec], _ptr(lrd), _ptr(local), _ptr(site), _ptr(mean), _stream()))
+        return (lrd, local, mean, site) if want_sites else (lrd, local, mean)
 
     def purity(self, arch: dict, params, n: int, alpha, beta, prec="fp32"):
         """[purity estimate, mean sign] (float64, device) from pairs (alpha_p, beta_p)."""

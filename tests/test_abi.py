@@ -61,7 +61,7 @@ def test_new_entry_points_validate_before_any_device_call():
     assert L.tdo_sr_solve(None, None, 4, 10, None, None, 1e-3, 10, None, None, st) != 0
     assert "ctx" in L.tdo_last_error().decode()
     arch = tdo.arch_t(dict(d=16, heads=2, layers=1, mlp=64))
-    assert L.tdo_observables(None, ctypes.byref(arch), None, 4, None, 0, 0, None, None, None, st) != 0
+    assert L.tdo_observables(None, ctypes.byref(arch), None, 4, None, 0, 0, None, None, None, None, st) != 0
     assert L.tdo_purity(None, ctypes.byref(arch), None, 4, None, None, 1, 0, None, st) != 0
     assert L.tdo_sample_diag(None, ctypes.byref(arch), None, 4, 1, None, None, 0, None, 1, 0, None, st) != 0
     assert L.tdo_log_rho_jacobian(None, ctypes.byref(arch), None, 4, None, 1, 0, None, st) != 0

@@ -88,11 +88,16 @@ def test_local_estimators_and_mean(gpu, prec, name, n, B):
     params = synth.params(arch, 40 + n, "stress")
     a = alphas(n, B, 41 + n)
     ctx = gpu.Ctx(0)
-    lrd, local, mean = ctx.observables(arch, cuda(params), n, cuda(a), prec)
-    lrd, local, mean = lrd.cpu().numpy(), local.cpu().numpy(), mean.cpu().numpy()
+    lrd, local, mean, site = ctx.observables(arch, cuda(params), n, cuda(a), prec, want_sites=True)
+    lrd, local, mean, site = lrd.cpu().numpy(), local.cpu().numpy(), mean.cpu().numpy(), site.cpu().numpy()
     ref = oracle_local(params, arch, n, a)
     check_local(local, lrd, ref, prec, f"{name} n={n} B={B}")
     est, lr, kd, ko = ref
+    # per site: the same bound with that site's ratio, sigma^z exact
+    gs = site[..., 0] + 1j * site[..., 1]
+    serr = np.abs(gs - est)[:, :, :2] / (1.0 + np.abs(est[:, :, 0:1]) * (ko + kd[:, None])[:, :, None])
+    assert serr.max() < TOL[prec], serr.max()
+    assert np.array_equal(site[:, :, 2, 0], est[:, :, 2].real.astype(np.float32))
     want, msign = ob.sampled_expectation(lr, est)
     got = mean[0:6:2] + 1j * mean[1:6:2]
     flips = np.sum(((np.abs(lrd[:, 1]) > 1.0) != (np.abs(lr.imag) > 1.0)))
