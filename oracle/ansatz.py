@@ -30,11 +30,17 @@ Parameters are one flat real vector, row-major, x @ W convention, in the order
 returned by ``param_layout``.
 
 Parity: unpinned by printed values (the paper prints no weights or outputs).
-Pinned by invariants and independent re-derivations in
-tests/test_oracle_ansatz.py: cyclic-shift invariance, Hermiticity, closed form
-of the symmetrisation when the head weights vanish, the convolution against
+Pinned by invariants, closed forms and independent re-derivations in
+tests/test_oracle_ansatz.py: cyclic-shift invariance, Hermiticity, the closed
+form of the symmetrisation when the head weights vanish, n-independence of log
+rho at uniform configurations (the 1/N mean pooling), the convolution against
 torch's own circular conv2d, the attention block against
-torch.nn.MultiheadAttention, the MLP against torch.nn.Linear/ReLU, and parameter-layout independence of N.
+torch.nn.MultiheadAttention, the MLP against torch.nn.Linear/ReLU, the whole
+network against a second assembly from torch.nn modules (which fixes the
+composition: residual attention, then residual feed-forward, mean over sites,
+head), and parameter-layout independence of N.  Sum pooling, a dropped
+feed-forward residual and a swapped sub-layer order are planted there and
+each fails a pin.
 """
 from __future__ import annotations
 
