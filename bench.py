@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precs", default="fp32,bf16")
+    ap.add_argument("--fp32-steps", type=int, default=3,
+                    help="timed steps of the FP32 comparison leg (at most --steps; one step is about 17 s)")
     # 128 GiB of the 288 GB of HBM: fewer, larger chunks (each chunk pays the per-chunk
     # evaluation-list, loss and reduction launches and a launch tail per kernel)
     ap.add_argument("--workspace-gib", type=float, default=128.0)
@@ -142,7 +144,10 @@ def main():
     diag_present = (conn[:, 0, 0] == cfg[:, 0]) & (conn[:, 0, 1] == cfg[:, 1])
     E_step = int(ncon.sum().item()) + int((~diag_present).sum().item())
     del conn
-    units_step = 2 * (E_step + B)  # config-passes per layer per step (mode B adds one pass over the samples)
+    # configuration-passes per layer per step: two passes of every evaluated configuration.  Mode B's
+    # second forward and backward over the B samples (the centring term, formed once F is known)
+    # is implementation work and is not counted.
+    units_step = 2 * E_step
     log(f"bench: {E_step} configurations per step (K_avg {E_step / B:.2f})")
 
     if args.copy_calibration_mib:
@@ -174,7 +179,9 @@ def main():
     results = {}
     stream = torch.cuda.current_stream()
     for prec in [p for p in args.precs.split(",") if p]:
-        for i in range(args.warmup):
+        steps = args.steps if prec == "bf16" else max(1, min(args.steps, args.fp32_steps))
+        warmup = args.warmup if prec == "bf16" else min(args.warmup, 1)
+        for i in range(warmup):
             t0 = time.time()
             loss, grad, _ = ctx.loss_grad(arch, params, model, cfg, None, prec, "B")
             torch.cuda.synchronize()
@@ -183,23 +190,26 @@ def main():
         ctx.profile(True)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
-        for i in range(args.steps):
+        for i in range(steps):
             loss, grad, _ = ctx.loss_grad(arch, params, model, cfg, None, prec, "B")
-            if i == 0 or i == args.steps - 1:
+            if i == 0 or i == steps - 1:
                 log(f"bench: {prec} step {i} queued")
         ev1.record(stream)
         torch.cuda.synchronize()
         total_ms = ev0.elapsed_time(ev1)
         kt = {k: ctx.profile_read(k) for k in KERNELS}
         ctx.profile(False)
-        ms = total_ms / args.steps
-        r = dict(ms_per_step=ms, configs_per_s=E_step / (ms / 1e3), loss=float(loss[0]),
+        ms = total_ms / steps
+        r = dict(ms_per_step=ms, steps=steps, configs_per_s=E_step / (ms / 1e3), loss=float(loss[0]),
                  grad_norm=float(torch.linalg.vector_norm(grad).item()), kernels={})
         for k, (kms, cnt) in kt.items():
-            fl = kernel_flops_per_unit(k, n, d, m) * units_step * L * args.steps
+            fl = kernel_flops_per_unit(k, n, d, m) * units_step * L * steps
             r["kernels"][k] = dict(total_ms=kms, launches=cnt, avg_launch_ms=kms / max(cnt, 1),
                                    share=kms / total_ms, tflops=fl / (kms / 1e3) / 1e12 if kms > 0 else 0.0,
                                    flops_per_launch=fl / max(cnt, 1))
+        step_flops = sum(kernel_flops_per_unit(k, n, d, m) for k in KERNELS) * units_step * L
+        r["step"] = dict(flops=step_flops, tflops=step_flops / (ms / 1e3) / 1e12,
+                         frac_of_peak=step_flops / (ms / 1e3) / 1e12 / PEAK_TFLOPS[prec])
         results[prec] = r
         log(f"bench: {prec} {ms:.1f} ms/step, {r['configs_per_s'] / 1e6:.3f} M configs/s; kernels " +
             ", ".join(f"{k} {v['share'] * 100:.0f}% {v['tflops']:.0f} TF/s" for k, v in r["kernels"].items()))
@@ -213,34 +223,44 @@ def main():
                     frac=achieved / PEAK_TFLOPS[main_prec], traffic=recorded_traffic(dom, name),
                     avg_launch_ms=kd["avg_launch_ms"], flops_per_launch=kd["flops_per_launch"],
                     flops_per_unit=kernel_flops_per_unit(dom, n, d, m),
-                    unit_def="one configuration-pass through one layer")
+                    unit_def="one configuration-pass through one layer",
+                    whole_step_frac=R["step"]["frac_of_peak"], target_frac_n32=0.40)
 
     extras = None
     if not args.no_extras:
         extras = {"ising_n8": bench_small(ctx, tdo, synth, "ising_n8", args.steps),
                   "xyz_n16": bench_small(ctx, tdo, synth, "xyz_n16", args.steps),
                   "batched_uneven": bench_batched(ctx, tdo, synth, args.steps),
+                  "batched_uneven_fp32": bench_batched(ctx, tdo, synth, 1, "fp32"),
                   "sampler": bench_sampler(ctx, arch, params, n, synth),
                   "observables": bench_observables(ctx, arch, params, n, synth),
                   "ising2d_4x8": bench_lattice2d(ctx, synth),
                   "sr": bench_sr(ctx, arch, params, n, synth),
                   "lindblad": bench_lindblad(ctx, tdo, model, synth, args.steps)}
 
-    # the oracle leg (host): timed on a bounded sample, and (unless --no-check) the FP64 loss of
-    # 16 sampled rows of the same batch, against which the GPU losses on those rows are compared
-    cpu, F_ref = None, None
+    # the oracle leg (host): timed on a bounded sample, and (unless --no-check) the FP64 loss and
+    # gradient of 16 sampled rows of the same batch, at the benchmark's weights and at "mid" weights
+    # (where log rho varies across configurations, so that BF16 rounding shows), against which
+    # the GPU's loss and gradient on those rows are compared (weights zero on the other rows)
+    cpu, accuracy = None, None
     pick = np.sort(np.random.default_rng(7).choice(B, 16, replace=False))
     if not args.no_cpu_baseline:
-        cpu, F_ref = cpu_baseline(arch, model, params_np, cfg_np, None if args.no_check else pick)
-    loss_err = None
-    if F_ref is not None:
-        w = torch.zeros(B, dtype=torch.float64, device=dev)
-        w[torch.from_numpy(pick).to(dev)] = 1.0
-        loss_err = {}
-        for prec in results:
-            lg, _, _ = ctx.loss_grad(arch, params, model, cfg, w, prec, "B")
-            loss_err[prec] = abs(float(lg[0]) - F_ref) / abs(F_ref)
-        log(f"bench: loss rel. error vs FP64 oracle on 16 sampled rows: {loss_err}")
+        params_mid = synth.params(arch, wl["seed"], "mid")
+        cpu, refs = cpu_baseline(arch, model, params_np, cfg_np,
+                                 None if args.no_check else {"init": params_np, "mid": params_mid}, pick)
+        if refs:
+            w = torch.zeros(B, dtype=torch.float64, device=dev)
+            w[torch.from_numpy(pick).to(dev)] = 1.0
+            accuracy = {"rows": "16 uniformly drawn samples of the batch (ReLU kink units included)"}
+            for scale, (F_ref, g_ref) in refs.items():
+                p_dev = params if scale == "init" else torch.from_numpy(params_mid).to(dev)
+                accuracy[scale] = {}
+                for prec in results:
+                    lg, gg, _ = ctx.loss_grad(arch, p_dev, model, cfg, w, prec, "B")
+                    gerr = float(np.linalg.norm(gg.cpu().numpy() - g_ref) / np.linalg.norm(g_ref))
+                    accuracy[scale][prec] = {"loss_rel_err": abs(float(lg[0]) - F_ref) / abs(F_ref),
+                                             "grad_rel_l2_err": gerr}
+            log(f"bench: errors vs FP64 oracle on 16 sampled rows: {accuracy}")
 
     out = {
         "metric": METRIC,
@@ -261,7 +281,8 @@ def main():
         "fp32_value": results.get("fp32", {}).get("configs_per_s"),
         "speedup_bf16_over_fp32": (results["bf16"]["configs_per_s"] / results["fp32"]["configs_per_s"]
                                    if "bf16" in results and "fp32" in results else None),
-        "loss_rel_err_vs_oracle": loss_err,
+        "loss_rel_err_vs_oracle": ({p: v["loss_rel_err"] for p, v in accuracy["mid"].items()} if accuracy else None),
+        "errors_vs_oracle": accuracy,
         "per_precision": results,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -331,9 +352,9 @@ def bench_small(ctx, tdo, synth, name, steps):
     return res
 
 
-def bench_batched(ctx, tdo, synth, steps):
+def bench_batched(ctx, tdo, synth, steps, prec="bf16"):
     """64 problems (n in [8, 40], half Ising half XYZ, own parameters), 2048 samples
-    each, BF16, mode B, one tdo_loss_grad_batched call per step: eager call, recording
+    each, mode B, one tdo_loss_grad_batched call per step: eager call, recording
     call, then `steps` timed graph replays on a side stream."""
     import torch
     wl = synth.WORKLOADS["batched_uneven"]
@@ -349,19 +370,19 @@ def bench_batched(ctx, tdo, synth, steps):
         out = (torch.empty(len(models), dtype=torch.float64, device="cuda"),
                [torch.empty(P, dtype=torch.float64, device="cuda") for _ in models])
         for _ in range(2):  # eager (sizes, autotunes), then recorded
-            ctx.loss_grad_batched(arch, params, models, cfgs, None, "bf16", "B", out=out)
+            ctx.loss_grad_batched(arch, params, models, cfgs, None, prec, "B", out=out)
         s.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(s)
         for _ in range(steps):
-            ctx.loss_grad_batched(arch, params, models, cfgs, None, "bf16", "B", out=out)
+            ctx.loss_grad_batched(arch, params, models, cfgs, None, prec, "B", out=out)
         e1.record(s)
         s.synchronize()
     ms = e0.elapsed_time(e1) / steps
     log(f"bench: batched workload {len(models)} problems, {E} configurations: {ms:.1f} ms/step, "
-        f"{E / ms * 1e3 / 1e6:.3f} M configs/s (bf16, graph replay)")
+        f"{E / ms * 1e3 / 1e6:.3f} M configs/s ({prec}, graph replay)")
     return {"value": E / (ms / 1e3), "unit": "configs/s", "ms_per_step": ms, "configs_per_step": E,
-            "problems": len(models), "B": wl["B"], "dtype": "bf16", "steps": steps}
+            "problems": len(models), "B": wl["B"], "dtype": prec, "steps": steps}
 
 
 def bench_sampler(ctx, arch, params, n, synth):
@@ -547,11 +568,11 @@ def bench_lindblad(ctx, tdo, model, synth, steps, B=1 << 20):
     return {"B": B, "n": n, "kmax": kmax, "entries": entries, "kernels": res}
 
 
-def cpu_baseline(arch, model, params_np, cfg_np, pick=None):
+def cpu_baseline(arch, model, params_np, cfg_np, ref_params=None, pick=None):
     """The oracle leg: the FP64 oracle's loss and gradient (mode B) on a bounded
     prefix of the same samples, timed on the host and scaled to configurations per
-    second; and, when pick is given, the oracle's loss on those rows (untimed).
-    Returns (baseline dict, loss on pick or None)."""
+    second; and, for each named parameter vector in ref_params, the oracle's loss and
+    gradient on the rows in pick (untimed).  Returns (baseline dict, {name: (F, grad)})."""
     import numpy as np
     import torch
 
@@ -573,10 +594,20 @@ def cpu_baseline(arch, model, params_np, cfg_np, pick=None):
     S = int(min(max(2, round(2 * 15.0 / max(t, 1e-3))), 512))
     E, t = run(S)
     log(f"bench: oracle {S} samples ({E} configurations) in {t:.1f} s")
-    F_ref = float(vmc.loss(th, A, M, cfg_np[pick])[0]) if pick is not None else None
+    refs = {}
+    for name, p in (ref_params or {}).items():
+        F, g, _ = vmc.loss_grad(p.astype(np.float64), A, M, cfg_np[pick], None, mode="B")
+        refs[name] = (F, g)
+    cpu_model = ""
+    try:
+        cpu_model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return ({"value": E / t, "unit": "configs/s", "cores": torch.get_num_threads(), "kind": "oracle",
-             "sample": f"first {S} of the 65536 samples ({E} configurations), FP64 loss and gradient (mode B)"},
-            F_ref)
+             "host_cores": os.cpu_count(), "host_cpu": cpu_model,
+             "sample": f"first {S} of the 65536 samples ({E} configurations), FP64 loss and gradient (mode B); "
+                       f"cores = the threads torch used"},
+            refs)
 
 
 if __name__ == "__main__":

@@ -19,6 +19,15 @@
  * - Calls are asynchronous on the given stream (NULL = the legacy default
  *   stream) unless stated otherwise; validation that needs only host data
  *   happens before any launch, and on error no kernel has been launched.
+ * - Calls that take network parameters first check them for inf and nan
+ *   (one read-only kernel on the stream, whose count the call waits for; the
+ *   check is skipped while the stream is being captured into a graph) and
+ *   return TDO_ENONFINITE with nothing else launched if any is found.
+ * - Calls on one context share its workspace.  A call made on a different
+ *   stream than the previous one waits (hipStreamWaitEvent, no host wait)
+ *   for the end of that previous call before it touches the workspace, so a
+ *   context may be used from several streams; its calls then run one after
+ *   another.  Contexts are not thread-safe: one host thread at a time.
  * - Return value: TDO_OK (0) or a negative error code; the message of the
  *   last error of the calling thread is returned by tdo_last_error().
  *   Nothing aborts and no C++ exception crosses this interface.
@@ -40,15 +49,26 @@ extern "C" {
 #define TDO_ENOMEM (-2)       /* workspace budget too small or allocation failed */
 #define TDO_EHIP (-3)         /* a HIP runtime call failed */
 #define TDO_EUNSUPPORTED (-4) /* valid request outside what the library implements */
+#define TDO_ENONFINITE (-5)   /* a network parameter is inf or nan; nothing computed */
+
+/* Activation set of the network (tdo_arch_t.act).  TDO_ACT_RELU_FFN: exact GELU
+ * u Phi(u) after each of the two embedding convolutions (Eq. circ-conv, the
+ * second "in the same manner"), ReLU in the feed-forward sub-layer (the paper's
+ * transformer block has none; it follows the position-wise feed-forward network
+ * of the transformer it builds on).  The only set the kernels implement. */
+#define TDO_ACT_RELU_FFN 0
 
 /* Network shape.  d = width C2 of the site embeddings and attention
  * (main text, "Transformer density operator ansatz"; App. B), heads = number
  * of attention heads (d % heads == 0), layers = number of stacked
  * [attention + MLP] blocks, mlp = hidden width of the residual MLP.
+ * c1 = number of filters of the first embedding convolution (App. B, C1);
+ * 0 means c1 = d.  act = activation set (TDO_ACT_*).
  * Supported: d in {16, 32, 64}, d/heads in {8, 16}, mlp a multiple of 32 with
- * mlp <= 512, 1 <= layers <= 16. */
+ * mlp <= 512, 1 <= layers <= 16, c1 in {0, d}, act = TDO_ACT_RELU_FFN; other
+ * values return TDO_EUNSUPPORTED. */
 typedef struct {
-    int32_t d, heads, layers, mlp;
+    int32_t d, heads, layers, mlp, c1, act;
 } tdo_arch_t;
 
 /* Dissipative spin chain with periodic bonds and jumps sqrt(gamma) sigma^-_i.

@@ -84,6 +84,78 @@ ProfScope::~ProfScope() {
   p->recs.push_back({name, start, stop});
 }
 
+// ---------------------------------------------------------------- ordering and parameter checks
+int32_t WsOrder::begin(Context* c_, hipStream_t st_) {
+  c = c_;
+  st = st_;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  TDO_HIP(hipStreamIsCapturing(st, &cap));
+  active = cap == hipStreamCaptureStatusNone;
+  if (active && c->ws_recorded && c->ws_stream != st) TDO_HIP(hipStreamWaitEvent(st, c->ws_done, 0));
+  return TDO_OK;
+}
+
+WsOrder::~WsOrder() {
+  if (!active || !c->ws_done) return;
+  if (hipEventRecord(c->ws_done, st) == hipSuccess) {
+    c->ws_stream = st;
+    c->ws_recorded = true;
+  } else {
+    (void)hipGetLastError();
+  }
+}
+
+// One workgroup counts the values whose exponent field is all ones (inf or nan) and
+// writes (or adds) the count: a fixed-size read of a parameter vector, a few microseconds.
+__global__ void __launch_bounds__(1024) k_count_nonfinite(const float* __restrict__ p, int64_t n, int accumulate,
+                                                          uint32_t* __restrict__ out) {
+  __shared__ uint32_t part[16];
+  uint32_t cnt = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+    cnt += ((__float_as_uint(p[i]) & 0x7f800000u) == 0x7f800000u) ? 1u : 0u;
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, WAVE);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+    out[0] = accumulate ? out[0] + t : t;
+  }
+}
+
+static bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cap != hipStreamCaptureStatusNone;
+}
+
+int32_t count_nonfinite(Context* c, const float* p, int64_t n, bool accumulate, hipStream_t st) {
+  if (capturing(st)) return TDO_OK;
+  if (!c->nf_dev) {
+    TDO_HIP(hipMalloc(&c->nf_dev, 256));
+    TDO_HIP(hipHostMalloc(&c->nf_host, 256, hipHostMallocDefault));
+  }
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(1), dim3(1024), 0, st, p, n, accumulate ? 1 : 0, c->nf_dev);
+  TDO_HIP(hipGetLastError());
+  return TDO_OK;
+}
+
+int32_t check_nonfinite(Context* c, hipStream_t st, const char* what) {
+  if (capturing(st) || !c->nf_dev) return TDO_OK;
+  TDO_HIP(hipMemcpyAsync(c->nf_host, c->nf_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  TDO_HIP(hipStreamSynchronize(st));
+  TDO_CHECK(c->nf_host[0] == 0, TDO_ENONFINITE, "%s: %u parameter values are inf or nan", what, c->nf_host[0]);
+  return TDO_OK;
+}
+
+int32_t check_params_finite(Context* c, const float* p, int64_t n, hipStream_t st) {
+  TDO_TRY(count_nonfinite(c, p, n, false, st));
+  return check_nonfinite(c, st, "params");
+}
+
 int32_t ensure_workspace(Context* c, size_t bytes) {
   if (bytes <= c->ws_size) return TDO_OK;
   TDO_CHECK(bytes <= c->budget, TDO_ENOMEM, "workspace of %zu bytes exceeds the context budget of %zu bytes",
@@ -224,6 +296,11 @@ int32_t tdo_ctx_create(tdo_ctx_t** ctx, int32_t device, size_t workspace_bytes) 
   c->c.device = device;
   c->c.num_cus = prop.multiProcessorCount;
   c->c.budget = workspace_bytes ? workspace_bytes : (size_t(8) << 30);
+  if (hipEventCreateWithFlags(&c->c.ws_done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return set_error(TDO_EHIP, "hipEventCreateWithFlags failed");
+  }
   *ctx = c;
   return TDO_OK;
 }
@@ -236,6 +313,9 @@ int32_t tdo_ctx_destroy(tdo_ctx_t* ctx) {
   ctx->c.prof.destroy();
   if (ctx->c.graph.exec) TDO_HIP(hipGraphExecDestroy(ctx->c.graph.exec));
   if (ctx->c.ws) TDO_HIP(hipFree(ctx->c.ws));
+  if (ctx->c.nf_dev) TDO_HIP(hipFree(ctx->c.nf_dev));
+  if (ctx->c.nf_host) TDO_HIP(hipHostFree(ctx->c.nf_host));
+  if (ctx->c.ws_done) TDO_HIP(hipEventDestroy(ctx->c.ws_done));
   delete ctx;
   return TDO_OK;
 }
@@ -315,6 +395,9 @@ int32_t tdo_log_rho(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params,
   TDO_CHECK(params && cfg && log_rho, TDO_EINVAL, "NULL buffer");
   TDO_HIP(hipSetDevice(ctx->c.device));
   Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
   Arena ar;
   size_t woff[4];
   carve_weights(np, ar, woff);

@@ -106,6 +106,10 @@ extern "C" int32_t tdo_loss_grad_batched(tdo_ctx_t* ctx, const tdo_arch_t* arch,
     if (s != TDO_OK) return set_error(s, "problem %d: %s", p, tdo_last_error());
     TDO_CHECK(params[p] && cfg[p] && grad[p], TDO_EINVAL, "problem %d: NULL buffer", p);
   }
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  for (int32_t p = 0; p < n_problems; ++p) TDO_TRY(count_nonfinite(&c, params[p], np[p].pp.nparams, p > 0, stream));
+  TDO_TRY(check_nonfinite(&c, stream, "params of the problems"));
   std::vector<uint8_t> key;
   put(key, *arch);
   put(key, n_problems);

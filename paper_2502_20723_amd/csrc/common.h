@@ -97,7 +97,35 @@ struct Context {
   Profiler prof;
   GraphCache graph;
   std::vector<TuneEntry> tune;
+  // count of non-finite parameters (device) and its pinned host copy
+  uint32_t* nf_dev = nullptr;
+  uint32_t* nf_host = nullptr;
+  // recorded at the end of the last call that used the workspace, on the stream it ran on
+  hipEvent_t ws_done = nullptr;
+  hipStream_t ws_stream = nullptr;
+  bool ws_recorded = false;
 };
+
+// Orders calls that share the context's workspace across streams: the call's stream
+// first waits for the end of the previous call when that ran on another stream, and the
+// end of this call is recorded when the guard goes out of scope.  Inactive while the
+// stream is being captured into a graph (the library's own recording of the batched
+// call orders its launches by the capturing stream alone).
+struct WsOrder {
+  Context* c = nullptr;
+  hipStream_t st = nullptr;
+  bool active = false;
+  int32_t begin(Context* c_, hipStream_t st_);
+  ~WsOrder();
+};
+
+// Non-finite parameters: count them on the stream (a read-only kernel, one workgroup per
+// call; accumulate adds to the count of the previous call), then wait for the count.
+// Both are skipped while the stream is being captured.
+int32_t count_nonfinite(Context* c, const float* p, int64_t n, bool accumulate, hipStream_t st);
+int32_t check_nonfinite(Context* c, hipStream_t st, const char* what);
+// Both steps for one parameter vector.
+int32_t check_params_finite(Context* c, const float* p, int64_t n, hipStream_t st);
 
 // Grow the context workspace to at least `bytes` (<= budget).
 int32_t ensure_workspace(Context* c, size_t bytes);

@@ -14,6 +14,10 @@ int32_t make_pack_plan(const tdo_arch_t* arch, PackPlan* pp) {
   TDO_CHECK(d / H == 8 || d / H == 16, TDO_EUNSUPPORTED, "head width d/heads=%d not in {8, 16}", d / H);
   TDO_CHECK(m >= 32 && m % 32 == 0 && m <= 512, TDO_EUNSUPPORTED, "mlp=%d must be a multiple of 32 in [32, 512]", m);
   TDO_CHECK(L >= 1 && L <= 16, TDO_EUNSUPPORTED, "layers=%d not in [1, 16]", L);
+  TDO_CHECK(arch->c1 == 0 || arch->c1 == d, TDO_EUNSUPPORTED,
+            "conv-1 width c1=%d: the kernels implement c1 = d (0 selects it)", arch->c1);
+  TDO_CHECK(arch->act == TDO_ACT_RELU_FFN, TDO_EUNSUPPORTED,
+            "activation set %d: the kernels implement TDO_ACT_RELU_FFN (0) only", arch->act);
   PackPlan p{};
   p.d = d;
   p.D = d < 32 ? 32 : d;

@@ -250,6 +250,9 @@ int32_t tdo_observables(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* par
   TDO_CHECK(params && alpha && log_rho_diag && local, TDO_EINVAL, "NULL buffer");
   TDO_HIP(hipSetDevice(ctx->c.device));
   Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
   RowPlan rp;
   TDO_TRY(plan_rows(c, np, B, n + 1, 0, &rp));
   void* ws = c.ws;
@@ -287,6 +290,9 @@ int32_t tdo_purity(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params, 
   TDO_CHECK(params && alpha && beta && out, TDO_EINVAL, "NULL buffer");
   TDO_HIP(hipSetDevice(ctx->c.device));
   Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
   RowPlan rp;
   const size_t tail = (size_t)P * (sizeof(double) + sizeof(float)) + 256;
   TDO_TRY(plan_rows(c, np, P, 3, tail, &rp));

@@ -188,6 +188,9 @@ extern "C" int32_t tdo_sample(tdo_ctx_t* ctx, const tdo_arch_t* arch, const floa
   TDO_CHECK(params && state && state_log_rho && samples, TDO_EINVAL, "NULL buffer");
   TDO_HIP(hipSetDevice(ctx->c.device));
   Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
   ChainWs cw;
   TDO_TRY(plan_chains(c, np, chains, &cw));
   const int64_t chunk = cw.chunk;
@@ -244,6 +247,9 @@ extern "C" int32_t tdo_sample_diag(tdo_ctx_t* ctx, const tdo_arch_t* arch, const
   TDO_CHECK(params && state && state_log_rho && samples, TDO_EINVAL, "NULL buffer");
   TDO_HIP(hipSetDevice(ctx->c.device));
   Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
   ChainWs cw;
   TDO_TRY(plan_chains(c, np, chains, &cw));
   void* ws = c.ws;

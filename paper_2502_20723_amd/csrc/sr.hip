@@ -189,6 +189,8 @@ extern "C" int32_t tdo_sr_solve(tdo_ctx_t* ctx, double* jac, int64_t B, int64_t 
   TDO_CHECK(jac && grad && x, TDO_EINVAL, "NULL buffer");
   TDO_HIP(hipSetDevice(ctx->c.device));
   Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
   Arena ar;
   const size_t or_ = ar.take<double>((size_t)P), op = ar.take<double>((size_t)P), oap = ar.take<double>((size_t)P);
   const size_t oup = ar.take<double>(2 * (size_t)B * kSeg), ou = ar.take<double>(2 * (size_t)B);

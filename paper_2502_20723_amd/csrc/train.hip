@@ -281,6 +281,9 @@ extern "C" int32_t tdo_log_rho_vjp(tdo_ctx_t* ctx, const tdo_arch_t* arch, const
   TDO_CHECK(params && grad && (B == 0 || (cfg && seed)), TDO_EINVAL, "NULL buffer");
   TDO_HIP(hipSetDevice(ctx->c.device));
   Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
   TrainWs t;
   TDO_TRY(plan_train(c, np, std::max<int64_t>(B, 1), 1, &t));
   void* ws = c.ws;
@@ -321,6 +324,9 @@ extern "C" int32_t tdo_log_rho_jacobian(tdo_ctx_t* ctx, const tdo_arch_t* arch, 
   TDO_CHECK(params && cfg && jac, TDO_EINVAL, "NULL buffer");
   TDO_HIP(hipSetDevice(ctx->c.device));
   Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
   TrainWs t;
   TDO_TRY(plan_train(c, np, 1, 1, &t));
   // kLanes independent copies of the one-configuration scratch, each driven on its
@@ -471,5 +477,9 @@ extern "C" int32_t tdo_loss_grad(tdo_ctx_t* ctx, const tdo_arch_t* arch, const f
   TrainWs t;
   TDO_TRY(loss_grad_check(ctx->c, arch, model, B, prec, grad_mode, &m, &np, &t));
   TDO_CHECK(params && cfg && loss && grad, TDO_EINVAL, "NULL buffer");
-  return loss_grad_run(ctx->c, np, m, t, params, cfg, B, weights, grad_mode, loss, grad, lloc_out, stream);
+  Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
+  return loss_grad_run(c, np, m, t, params, cfg, B, weights, grad_mode, loss, grad, lloc_out, stream);
 }

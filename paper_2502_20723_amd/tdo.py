@@ -27,7 +27,7 @@ EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_erro
 
 
 class ArchT(ctypes.Structure):
-    _fields_ = [("d", ctypes.c_int32), ("heads", ctypes.c_int32), ("layers", ctypes.c_int32), ("mlp", ctypes.c_int32)]
+    _fields_ = [(k, ctypes.c_int32) for k in ("d", "heads", "layers", "mlp", "c1", "act")]
 
 
 class ModelT(ctypes.Structure):
@@ -96,8 +96,13 @@ def _check(code):
         raise TdoError(code, lib().tdo_last_error().decode())
 
 
+TDO_ENONFINITE = -5
+TDO_ACT_RELU_FFN = 0
+
+
 def arch_t(a: dict) -> ArchT:
-    return ArchT(int(a["d"]), int(a["heads"]), int(a["layers"]), int(a["mlp"]))
+    return ArchT(int(a["d"]), int(a["heads"]), int(a["layers"]), int(a["mlp"]), int(a.get("c1", 0) or 0),
+                 int(a.get("act", TDO_ACT_RELU_FFN)))
 
 
 def model_t(m: dict) -> ModelT:

@@ -13,10 +13,13 @@ The error of an emulation against the FP64 oracle is the error that precision
 incurs by itself; a GPU result is required to stay within a small factor of
 it.  It is not a reference for parity (the FP64 oracle is).
 
-``kink_sensitivity`` bounds a second effect of rounding on the gradient: the
-feed-forward ReLU decides a unit's branch from the sign of its pre-activation,
-and for a pre-activation within rounding distance of zero that sign is decided
-by summation order.
+``kink_sensitivity`` measures a second effect of rounding on the gradient:
+the feed-forward ReLU decides a unit's branch from the sign of its
+pre-activation, and for a pre-activation within rounding distance of zero that
+sign is decided by summation order.  ``kink_margins`` gives, per sample, the
+smallest relative distance of any pre-activation of its evaluated
+configurations from zero, so that tests can assert the stated FP32 gradient
+bar on samples that have no unit in that band.
 """
 import math
 
@@ -136,3 +139,44 @@ def kink_sensitivity(params, A, M, cfg, w, mode, g_ref, kappa=KINK_KAPPA):
     finally:
         oa.mlp = orig
     return float(np.linalg.norm(gk - g_ref) / max(np.linalg.norm(g_ref), 1e-300))
+
+
+def kink_margins(params, A, M, cfg):
+    """Per sample b: min over the layers, the sites, the hidden units and the evaluated
+    configurations of the row (the sample and its connected configurations) of
+    |u| / (|b1| + sum |x W1|), u the feed-forward pre-activation, in FP64."""
+    cfg = np.asarray(cfg, dtype=np.uint64).reshape(-1, 2)
+    rows = ol.connected(M, cfg)
+    rec = []
+    orig = oa.mlp
+
+    def mlp_rec(x, w1, b1, w2, b2):
+        u = x @ w1 + b1
+        scale = x.abs() @ w1.abs() + b1.abs()
+        # a unit whose summands all vanish sits on the kink itself: margin 0
+        r = torch.where(scale > 0, u.abs() / torch.where(scale > 0, scale, torch.ones_like(scale)), torch.zeros_like(u))
+        rec.append(r.amin(dim=(1, 2)))
+        return orig(x, w1, b1, w2, b2)
+
+    th = torch.as_tensor(np.asarray(params, dtype=np.float64))
+    out = np.empty(len(cfg))
+    oa.mlp = mlp_rec
+    try:
+        with torch.no_grad():
+            for b in range(len(cfg)):
+                rec.clear()
+                oa.log_rho(th, A, np.concatenate([cfg[b:b + 1], rows[b][0]], 0), M.n)
+                out[b] = min(float(r.min()) for r in rec)
+    finally:
+        oa.mlp = orig
+    return out
+
+
+def kink_free_configs(params, A, M, B, seed, kappa=KINK_KAPPA, pool=8):
+    """B samples (uniform bits, PCG64 seed) whose rows have no feed-forward pre-activation
+    within kappa of zero relative to its summands: the first B such among pool * B draws."""
+    rng = np.random.default_rng(seed)
+    cand = rng.integers(0, 1 << M.n, size=(pool * B, 2), dtype=np.uint64)
+    keep = cand[kink_margins(params, A, M, cand) > kappa][:B]
+    assert len(keep) == B, f"only {len(keep)} of {pool * B} candidate samples are outside the kink band"
+    return keep

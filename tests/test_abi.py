@@ -39,7 +39,8 @@ def test_num_params_matches_layout(name):
 def test_invalid_arch_is_rejected():
     bad = [dict(d=48, heads=4, layers=1, mlp=64), dict(d=64, heads=3, layers=1, mlp=64),
            dict(d=64, heads=2, layers=1, mlp=64), dict(d=64, heads=4, layers=0, mlp=64),
-           dict(d=64, heads=4, layers=1, mlp=40)]
+           dict(d=64, heads=4, layers=1, mlp=40), dict(d=64, heads=4, layers=1, mlp=64, c1=32),
+           dict(d=64, heads=4, layers=1, mlp=64, act=1)]
     for a in bad:
         with pytest.raises(tdo.TdoError):
             tdo.num_params(a)
@@ -65,3 +66,13 @@ def test_new_entry_points_validate_before_any_device_call():
     assert L.tdo_purity(None, ctypes.byref(arch), None, 4, None, None, 1, 0, None, st) != 0
     assert L.tdo_sample_diag(None, ctypes.byref(arch), None, 4, 1, None, None, 0, None, 1, 0, None, st) != 0
     assert L.tdo_log_rho_jacobian(None, ctypes.byref(arch), None, 4, None, 1, 0, None, st) != 0
+
+
+def test_arch_fields_and_status_codes():
+    """c1 = d and c1 = 0 (its default) describe the same network; the header's
+    TDO_ENONFINITE and TDO_ACT_RELU_FFN are the binding's values."""
+    a = dict(d=64, heads=4, layers=2, mlp=256)
+    assert tdo.num_params(dict(a, c1=64)) == tdo.num_params(a) == oa.num_params(oa.Arch(**a))
+    src = open(os.path.join(ROOT, "include", "tdo.h")).read()
+    assert re.search(r"#define TDO_ENONFINITE \((-?\d+)\)", src).group(1) == str(tdo.TDO_ENONFINITE)
+    assert re.search(r"#define TDO_ACT_RELU_FFN (\d+)", src).group(1) == str(tdo.TDO_ACT_RELU_FFN)

@@ -5,7 +5,9 @@ from oracle import ansatz as oa
 from oracle import lindblad as ol
 from oracle import vmc
 from paper_2502_20723_amd import synth
-from tests.bf16_emulation import kink_sensitivity
+import pytest
+
+from tests.bf16_emulation import kink_free_configs, kink_margins, kink_sensitivity
 
 
 def _case():
@@ -31,3 +33,21 @@ def test_kink_sensitivity_full_band_moves_the_gradient():
     """With every unit in the band all ReLU branches switch, which changes the gradient."""
     params, arch, model, cfg, w, g = _case()
     assert kink_sensitivity(params, arch, model, cfg, w, "B", g, kappa=2.0) > 1e-2
+
+
+def test_kink_margins_bounds_and_a_planted_kink():
+    """|u| <= |b1| + sum |x W1| puts every margin in [0, 1]; a hidden unit with zero weights
+    and bias sits on the kink in every row (margin 0), so no sample is kink-free; the
+    oracle's feed-forward function is restored afterwards."""
+    params, arch, model, cfg, w, g = _case()
+    orig = oa.mlp
+    m = kink_margins(params, arch, model, cfg)
+    assert oa.mlp is orig
+    assert np.all((m > 0) & (m <= 1))
+    p = oa.unflatten(__import__("torch").as_tensor(params.copy()), arch)
+    p["l0_w1"][:, 3] = 0.0
+    p["l0_b1"][3] = 0.0
+    planted = np.concatenate([v.reshape(-1).numpy() for v in p.values()])
+    assert np.all(kink_margins(planted, arch, model, cfg) == 0)
+    with pytest.raises(AssertionError):
+        kink_free_configs(planted, arch, model, 2, 9)

@@ -14,8 +14,10 @@ ARCH = {k: synth.WORKLOADS[k]["arch"] for k in synth.WORKLOADS}
 # Stated tolerances for the workloads' init and the well-conditioned mid scale;
 # at the ill-conditioned stress scale the FP32 tolerance is derived from the
 # FP32 CPU evaluation of the oracle (6e-6 at N = 32, x16 margin for a
-# different summation order), and the BF16 one from the BF16 rounding
-# emulation of the same inputs (1.5x its error, at least 2e-2).
+# different summation order).  BF16 at the stress scale: within the stated 2e-2,
+# or, where BF16 rounding itself is further off (the BF16 emulation of the same
+# inputs, error e against FP64), within 0.5 e of the emulated log rho and, while
+# 1.5 e < 0.5, within 1.5 e of the oracle.
 TOL = {("init", "fp32"): 1e-5, ("init", "bf16"): 2e-2, ("mid", "fp32"): 1e-5, ("mid", "bf16"): 2e-2,
        ("stress", "fp32"): 1e-4, ("stress", "bf16"): None}
 
@@ -42,11 +44,16 @@ def test_log_rho_parity(gpu, name, n, B, scale, prec):
     err = log_rho_err(got, ref)
     print(f"{name} n={n} B={B} {scale} {prec}: err {err:.3e}")
     tol = TOL[(scale, prec)]
-    if tol is None:
-        emu = log_rho_err(log_rho_bf16(params, oa.Arch(**arch), cfg, n), ref)
-        tol = max(2e-2, 1.5 * emu)
-        print(f"  bf16 emulation err {emu:.3e} -> tolerance {tol:.3e}")
-    assert err < tol
+    if tol is not None:
+        assert err < tol
+        return
+    emu_lr = log_rho_bf16(params, oa.Arch(**arch), cfg, n)
+    emu, dist = log_rho_err(emu_lr, ref), log_rho_err(got, emu_lr)
+    print(f"  bf16 emulation err {emu:.3e}, GPU distance to the emulation {dist:.3e}")
+    if err >= 2e-2:
+        assert dist < 0.5 * emu
+        if 1.5 * emu < 0.5:
+            assert err < 1.5 * emu
 
 
 def test_log_rho_empty_batch(gpu):
