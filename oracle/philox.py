@@ -8,7 +8,7 @@ mixes the high halves with the other counter words and the round key; the key
 is advanced by the two Weyl constants between rounds.
 
 Parity: pinned by the published known-answer vectors in
-tests/test_oracle_philox.py.
+tests/test_oracle_philox_sampler.py.
 """
 from __future__ import annotations
 
