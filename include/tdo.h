@@ -322,6 +322,24 @@ int32_t tdo_sr_solve(tdo_ctx_t *ctx, double *jac, int64_t B, int64_t P, const do
                      const double *grad, double lambda, int32_t iters, double *x, double *info,
                      hipStream_t stream);
 
+/* log rho exactly as tdo_log_rho computes it, without allocating device memory:
+ * for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The work memory is a fixed array of
+ * TDO_NOALLOC_SCRATCH_BYTES in the library's device image, one per device, held
+ * until the process ends; its device address is looked up when a context is
+ * created on the device (tdo_ctx_create), so ctx must be a context of the device
+ * that holds params, cfg and log_rho (its workspace is not used).  Batches of any
+ * size run in chunks that fit the array; TDO_ENOMEM if the packed weights alone
+ * do not (never for the supported architectures: at most 5.3 MB).  The call
+ * launches kernels only: no allocation, no host wait, no parameter check (inf or
+ * nan parameters give non-finite results).  Every call on one device uses the
+ * same array: calls that overlap in time on one device (other streams, other
+ * threads) race and give wrong results; calls ordered on one stream are safe. */
+#define TDO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int32_t tdo_log_rho_noalloc(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                            const uint64_t *cfg, int64_t B, tdo_prec_t prec, float *log_rho,
+                            hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

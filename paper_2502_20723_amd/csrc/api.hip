@@ -296,6 +296,13 @@ int32_t tdo_ctx_create(tdo_ctx_t** ctx, int32_t device, size_t workspace_bytes) 
   c->c.device = device;
   c->c.num_cus = prop.multiProcessorCount;
   c->c.budget = workspace_bytes ? workspace_bytes : (size_t(8) << 30);
+  {
+    const int32_t s = noalloc_setup(device);
+    if (s != TDO_OK) {
+      delete c;
+      return s;
+    }
+  }
   if (hipEventCreateWithFlags(&c->c.ws_done, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     delete c;

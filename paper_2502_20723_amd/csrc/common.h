@@ -127,6 +127,9 @@ int32_t check_nonfinite(Context* c, hipStream_t st, const char* what);
 // Both steps for one parameter vector.
 int32_t check_params_finite(Context* c, const float* p, int64_t n, hipStream_t st);
 
+// Device address of the no-allocation scratch array on a device, looked up once per device.
+int32_t noalloc_setup(int device);
+
 // Grow the context workspace to at least `bytes` (<= budget).
 int32_t ensure_workspace(Context* c, size_t bytes);
 

@@ -23,7 +23,7 @@ EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_erro
            "tdo_profile_read", "tdo_connected", "tdo_local_lindbladian", "tdo_log_rho", "tdo_log_rho_vjp",
            "tdo_loss_grad", "tdo_loss_grad_batched", "tdo_sample", "tdo_sample_diag", "tdo_observables",
            "tdo_purity", "tdo_lr_schedule", "tdo_sgd_step", "tdo_adam_step", "tdo_log_rho_jacobian",
-           "tdo_sr_solve")
+           "tdo_sr_solve", "tdo_log_rho_noalloc")
 
 
 class ArchT(ctypes.Structure):
@@ -63,6 +63,7 @@ def lib() -> ctypes.CDLL:
         L.tdo_connected.argtypes = [vp, ctypes.POINTER(ModelT), vp, i64, i32, vp, vp, vp, vp]
         L.tdo_local_lindbladian.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp]
         L.tdo_log_rho.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp]
+        L.tdo_log_rho_noalloc.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp]
         L.tdo_log_rho_vjp.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp, vp]
         L.tdo_loss_grad.argtypes = [vp, ctypes.POINTER(ArchT), vp, ctypes.POINTER(ModelT), vp, i64, vp, i32, i32,
                                     vp, vp, vp, vp]
@@ -223,6 +224,17 @@ class Ctx:
         out = torch.empty((B, 2), dtype=torch.float32, device=cfg.device)
         _check(lib().tdo_log_rho(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(cfg), B, PREC[prec],
                                  _ptr(out), _stream()))
+        return out
+
+    def log_rho_noalloc(self, arch: dict, params, n: int, cfg, out, prec="fp32"):
+        """log rho into the caller's out (device float32 [B, 2]) through the entry point that
+        allocates no device memory."""
+        B = cfg.shape[0]
+        _dev(params, torch.float32, (num_params(arch),), "params")
+        _dev(cfg, torch.uint64, (B, 2), "cfg")
+        _dev(out, torch.float32, (B, 2), "out")
+        _check(lib().tdo_log_rho_noalloc(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(cfg), B,
+                                         PREC[prec], _ptr(out), _stream()))
         return out
 
     def log_rho_vjp(self, arch: dict, params, n: int, cfg, seed, prec="fp32"):

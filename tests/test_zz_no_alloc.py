@@ -1,0 +1,41 @@
+"""The entry point that allocates no device memory (tdo_log_rho_noalloc, for callers
+that cannot allocate) against tdo_log_rho, through the C-ABI: two calls in a row on
+one context, the second with a smaller batch (and another chain length), each equal
+to tdo_log_rho on the same inputs within the stated log rho bars (1e-5 relative in
+FP32, 2e-2 in BF16; the kernels are the same, so the results are expected to be
+identical), with the device's free memory unchanged across the second call."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2502_20723_amd import synth
+from tests.parity import log_rho_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16": 2e-2}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_noalloc_matches_log_rho_twice(gpu, prec):
+    arch = synth.WORKLOADS["ising_n32"]["arch"]
+    params = torch.from_numpy(synth.params(arch, 91, "mid")).cuda()
+    ctx = gpu.Ctx(0)
+    # first call: n = 32, 5000 configurations (more than one chunk of the scratch array);
+    # second call: n = 7 (four configurations per block), 333 configurations
+    for n, B in ((32, 5000), (7, 333)):
+        cfg = torch.from_numpy(synth.configs(n, B, 92 + n)).cuda()
+        ref = ctx.log_rho(arch, params, n, cfg, prec)
+        out = torch.full((B, 2), float("nan"), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        ctx.log_rho_noalloc(arch, params, n, cfg, out, prec)
+        torch.cuda.synchronize()
+        free1 = torch.cuda.mem_get_info()[0]
+        r = ref.cpu().numpy()
+        err = log_rho_err(out.cpu().numpy(), r[:, 0] + 1j * r[:, 1])
+        same = bool(torch.equal(out, ref))
+        print(f"noalloc {prec} n={n} B={B}: max rel diff to tdo_log_rho {err:.3e}, identical {same}, "
+              f"free memory change {free1 - free0} bytes")
+        assert err < TOL[prec]
+        assert free1 == free0
