@@ -178,6 +178,12 @@ def main():
 
     results = {}
     stream = torch.cuda.current_stream()
+    tuned = {}
+    for prec in [p for p in args.precs.split(",") if p]:
+        # the library's tile-shape tuner for this workload (untimed; the timed steps use its choice)
+        fw, fg, mw = ctx.autotune(arch, params, model, cfg, prec, "B")
+        tuned[prec] = {"fwd_waves_per_workgroup": fw, "fwd_workgroups_per_cu": fg, "bwd_mlp_waves_per_workgroup": mw}
+        log(f"bench: {prec} tuned shapes {tuned[prec]}")
     for prec in [p for p in args.precs.split(",") if p]:
         steps = args.steps if prec == "bf16" else max(1, min(args.steps, args.fp32_steps))
         warmup = args.warmup if prec == "bf16" else min(args.warmup, 1)
@@ -200,7 +206,8 @@ def main():
         kt = {k: ctx.profile_read(k) for k in KERNELS}
         ctx.profile(False)
         ms = total_ms / steps
-        r = dict(ms_per_step=ms, steps=steps, configs_per_s=E_step / (ms / 1e3), loss=float(loss[0]),
+        r = dict(ms_per_step=ms, steps=steps, tuned_shapes=tuned[prec], configs_per_s=E_step / (ms / 1e3),
+                 loss=float(loss[0]),
                  grad_norm=float(torch.linalg.vector_norm(grad).item()), kernels={})
         for k, (kms, cnt) in kt.items():
             fl = kernel_flops_per_unit(k, n, d, m) * units_step * L * steps
@@ -439,6 +446,19 @@ def bench_sr(ctx, arch, params, n, synth, B=256, iters=100):
     ctx.sr_solve(J.clone(), g, 1e-3, 2)
     ms_s, (x, info) = timed(lambda: ctx.sr_solve(J, g, 1e-3, iters))
     res = float(info.cpu()[0])
+    # the matrix-free form at the loss-gradient batch: no Jacobian stored; per CG iteration one
+    # forward-mode pass (FP32) and one reverse-mode pass over all the samples
+    Bf, it_f = 65536, 4
+    cfg_f = torch.from_numpy(synth.configs(n, Bf, 7002)).cuda()
+    tan = torch.from_numpy(np.random.default_rng(7003).standard_normal(P) * 0.1).cuda()
+    ctx.log_rho_jvp(arch, params, n, cfg_f[:64], tan)
+    ms_jvp, _ = timed(lambda: ctx.log_rho_jvp(arch, params, n, cfg_f, tan))
+    mf = {"B": Bf, "jvp_ms": ms_jvp, "jvp_configs_per_s": Bf / (ms_jvp / 1e3)}
+    for prec in ("fp32", "bf16"):
+        ms_mf, (xm, infom) = timed(lambda: ctx.sr_solve_matfree(arch, params, n, cfg_f, g, 1e-3, it_f, None, prec))
+        mf[prec] = {"cg_iters": it_f, "ms": ms_mf, "ms_per_iter": ms_mf / it_f, "residual": float(infom.cpu()[0])}
+    log(f"bench: SR matrix-free B={Bf}: jvp {ms_jvp:.1f} ms, CG iteration fp32 {mf['fp32']['ms_per_iter']:.1f} ms, "
+        f"bf16 {mf['bf16']['ms_per_iter']:.1f} ms")
     it_bytes = 2 * (2 * B) * P * 8 + 6 * P * 8
     gbs = iters * it_bytes / (ms_s / 1e3) / 1e9
     log(f"bench: SR n={n} B={B} P={P}: jacobian {ms_j:.1f} ms ({2 * B / (ms_j / 1e3):.0f} rows/s; bf16 "
@@ -446,7 +466,8 @@ def bench_sr(ctx, arch, params, n, synth, B=256, iters=100):
         f"{iters} CG iterations {ms_s:.1f} ms ({gbs:.0f} GB/s algorithmic), residual {res:.2e}")
     return {"B": B, "P": P, "jacobian_ms": ms_j, "jacobian_rows_per_s": 2 * B / (ms_j / 1e3),
             "jacobian_bf16_ms": ms_jb, "jacobian_bf16_max_row_rel_diff_vs_fp32": jb_err, "cg_iters": iters,
-            "cg_ms": ms_s, "cg_GB/s": gbs, "cg_frac_of_8TB/s": gbs / 8000.0, "residual": res, "lambda": 1e-3}
+            "cg_ms": ms_s, "cg_GB/s": gbs, "cg_frac_of_8TB/s": gbs / 8000.0, "residual": res, "lambda": 1e-3,
+            "matrix_free": mf}
 
 
 def bench_lattice2d(ctx, synth, B=16384):

@@ -204,6 +204,26 @@ int32_t tdo_loss_grad_batched(tdo_ctx_t *ctx, const tdo_arch_t *arch, int32_t n_
                               const double *const *weights, tdo_prec_t prec, int32_t grad_mode,
                               double *loss, double *const *grad, hipStream_t stream);
 
+/* Tile shapes of the loss/gradient kernels for one problem's shape (chain length,
+ * precision, width, head width, depth, MLP width), chosen by timing: the forward
+ * layer kernel's waves per workgroup (8: two per SIMD sharing the LDS weights,
+ * BF16 with n <= 32 only; or 4) and workgroups per CU (1 or 2), timed on the
+ * forward over the samples; the BF16 feed-forward backward's waves per workgroup
+ * at MLP width 256 (8 or 4), timed on whole loss/gradient evaluations, which
+ * write loss and grad (device double [1] and [P]).  The choice is kept in the
+ * context and used by every later call of that shape (tdo_loss_grad_batched
+ * tunes its problems the same way on its first call); when the environment
+ * variable TDO_AUTOTUNE_CACHE names a file when a context is created, tuned
+ * shapes are read from that JSON file and written back to it.  The forward
+ * shapes do not change results; the backward shape changes the order in which
+ * weight gradients are summed, so results of one context are reproducible but
+ * may differ by rounding from a context that tuned differently.  shapes: host
+ * int32 [3] or NULL: forward waves, forward workgroups per CU, backward waves.
+ * Waits on the host (event timing); not while the stream is captured. */
+int32_t tdo_autotune(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, const tdo_model_t *model,
+                     const uint64_t *cfg, int64_t B, tdo_prec_t prec, int32_t grad_mode, double *loss,
+                     double *grad, int32_t *shapes, hipStream_t stream);
+
 /* Metropolis-Hastings on P ~ |rho|^2 (App. C, "Efficient Sampling Strategy"),
  * `chains` independent chains, `sweeps` sweeps of 2n proposals each.  Proposal
  * t of chain c draws Philox4x32-10 (Salmon et al., SC'11) with counter
@@ -321,6 +341,31 @@ int32_t tdo_log_rho_jacobian(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float
 int32_t tdo_sr_solve(tdo_ctx_t *ctx, double *jac, int64_t B, int64_t P, const double *weights,
                      const double *grad, double lambda, int32_t iters, double *x, double *info,
                      hipStream_t stream);
+
+/* Jacobian-vector product of log rho (App. C, metric tensor of stochastic
+ * reconfiguration: the products O(x_b) . p that apply S without forming it):
+ *   jvp[b] = sum_k d log rho(x_b)/d theta_k tangent[k]   (complex: re, im),
+ * by forward-mode differentiation of the network in FP32 (the tangent of every
+ * stage evaluated with its value; not the fused MFMA kernels).  tangent: device
+ * double [P]; jvp: device float [B][2].  3 <= n <= 64. */
+int32_t tdo_log_rho_jvp(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                        const uint64_t *cfg, int64_t B, const double *tangent, float *jvp,
+                        hipStream_t stream);
+
+/* Stochastic reconfiguration without the Jacobian (App. C, metric tensor and
+ * hybrid update): the same solve as tdo_sr_solve, x = (S + lambda I)^-1 grad by
+ * conjugate gradients from x = 0 for exactly `iters` iterations, with S applied
+ * as S p = J^T (J p): per iteration one forward-mode pass over the samples
+ * (tdo_log_rho_jvp, FP32) and one reverse-mode pass (tdo_log_rho_vjp in
+ * precision prec) with the seeds w_b (t_b - sum_b' w_b' t_b'), t = J p, w the
+ * weights normalised to sum 1.  Nothing of size B x P is stored, so B is bounded
+ * only by the workspace chunking.  cfg: device uint64 [B][2]; weights: device
+ * double [B] (non-negative, positive sum) or NULL; grad, x: device double [P];
+ * info: device double [2] or NULL (relative residual of the recurrence, |g|). */
+int32_t tdo_sr_solve_matfree(tdo_ctx_t *ctx, const tdo_arch_t *arch, const float *params, int32_t n,
+                             const uint64_t *cfg, int64_t B, const double *weights, tdo_prec_t prec,
+                             const double *grad, double lambda, int32_t iters, double *x, double *info,
+                             hipStream_t stream);
 
 /* log rho exactly as tdo_log_rho computes it, without allocating device memory:
  * for callers that cannot allocate (code under HIP graph capture, tight serving

@@ -199,9 +199,15 @@ int32_t net_plan(const Context* c, const tdo_arch_t* arch, int n, bool bf16, Net
   np->num_cus = c->num_cus;
   np->prof = const_cast<Profiler*>(&c->prof);
   np->fwd_wg_per_cu = 1;
+  np->fwd_waves = (bf16 && !np->span) ? 8 : 4;
+  np->mlp_waves = (bf16 && np->pp.M == 256) ? 8 : 4;
   const uint64_t key = tune_key(*np);
   for (const TuneEntry& e : c->tune)
-    if (e.key == key) np->fwd_wg_per_cu = e.fwd_wg_per_cu;
+    if (e.key == key) {
+      np->fwd_wg_per_cu = e.fwd_wg_per_cu;
+      np->fwd_waves = e.fwd_waves;
+      np->mlp_waves = e.mlp_waves;
+    }
   return TDO_OK;
 }
 
@@ -241,6 +247,7 @@ int32_t run_forward(const NetPlan& np, const NetWeights& w, const uint64_t* ecfg
     a.last = l == L - 1;
     a.masked = np.masked;
     a.blocks_per_cu = np.fwd_wg_per_cu;
+    a.waves = np.fwd_waves;
     ProfScope ps(np.prof, "fwd_layer", st);
     TDO_TRY(launch_fwd_layer(a, np.bf16, np.D, np.DH, np.span, np.num_cus, st));
   }
@@ -296,6 +303,7 @@ int32_t tdo_ctx_create(tdo_ctx_t** ctx, int32_t device, size_t workspace_bytes) 
   c->c.device = device;
   c->c.num_cus = prop.multiProcessorCount;
   c->c.budget = workspace_bytes ? workspace_bytes : (size_t(8) << 30);
+  tune_cache_load(&c->c);
   {
     const int32_t s = noalloc_setup(device);
     if (s != TDO_OK) {

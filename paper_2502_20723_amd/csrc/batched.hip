@@ -6,12 +6,16 @@
 // so that the per-launch cost of the hundreds of small kernels of many problems
 // is paid once.
 //
-// The first (eager) call also autotunes, per distinct (chain length,
-// precision, width, head width, depth, MLP width), the number of workgroups per
-// CU of the forward layer kernel: each candidate runs the full forward over the
-// problem's first chunk of configurations and the fastest is kept in the context.
+// The first (eager) call also autotunes, per distinct (chain length, precision,
+// width, head width, depth, MLP width), the tile shapes of the forward layer kernel
+// (waves per workgroup, workgroups per CU) and of the BF16 feed-forward backward
+// (waves per workgroup); the fastest are kept in the context and, when
+// TDO_AUTOTUNE_CACHE names a file, in that JSON file, which later contexts read.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 
 #include "common.h"
 #include "lindblad.h"
@@ -28,15 +32,41 @@ void put(std::vector<uint8_t>& k, const T& v) {
   k.insert(k.end(), p, p + sizeof(T));
 }
 
-// Candidates and measurement of the forward grid.
-int32_t tune_forward(Context& c, NetPlan& np, const float* params, const uint64_t* cfg, int64_t E, hipStream_t st) {
+// Times fn() twice on the stream (the first run warms caches and code objects) and returns the
+// second duration in milliseconds, or a negative value on failure.
+template <class F>
+float time_twice(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F&& fn) {
+  float ms = -1.f;
+  for (int rep = 0; rep < 2; ++rep) {
+    if (hipEventRecord(e0, st) != hipSuccess) return -1.f;
+    if (fn() != TDO_OK) return -1.f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
+  }
+  return ms;
+}
+
+// Tile shapes of one problem's (chain length, precision, width, head width, depth, MLP width):
+//  1. the forward layer kernel: workgroups of 8 waves (two per SIMD, BF16 with n <= 32 only) or
+//     4 waves, and 1 or 2 workgroups per CU, timed on the full forward over the problem's
+//     samples;
+//  2. the BF16 feed-forward backward at MLP width 256: 8 or 4 waves per workgroup, timed on the
+//     whole loss and gradient of the problem (the backward cannot run alone), which writes the
+//     problem's outputs (the real call overwrites them).
+// The fastest shapes are kept in the context (and the cache file, if any).
+int32_t tune_problem(Context& c, NetPlan& np, const ModelDev& m, const TrainWs& t, const float* params,
+                     const uint64_t* cfg, int64_t B, const double* weights, int32_t grad_mode, double* loss,
+                     double* grad, hipStream_t st, bool* added) {
   const uint64_t key = tune_key(np);
   for (const TuneEntry& e : c.tune)
     if (e.key == key) {
       np.fwd_wg_per_cu = e.fwd_wg_per_cu;
+      np.fwd_waves = e.fwd_waves;
+      np.mlp_waves = e.mlp_waves;
       return TDO_OK;
     }
-  // workspace: weights, two residual buffers and z for the E configurations (a prefix of the samples)
+  const int64_t E = std::min<int64_t>(B, t.chunk);
+  // forward: weights, two residual buffers and z for the E samples
   Arena ar;
   size_t woff[4];
   carve_weights(np, ar, woff);
@@ -44,38 +74,51 @@ int32_t tune_forward(Context& c, NetPlan& np, const float* params, const uint64_
   const size_t oxa = ar.take<float>((size_t)nblk * 32 * np.D);
   const size_t oxb = ar.take<float>((size_t)nblk * 32 * np.D);
   const size_t oz = ar.take<float>((size_t)E * 4);
-  if (ar.used > c.ws_size) return TDO_OK;  // keep the default rather than grow the workspace for tuning
-  NetWeights w = weights_at(c.ws, woff);
-  TDO_TRY(pack_weights(np, params, &w, st));
+  if (ar.used > c.ws_size) return TDO_OK;  // keep the defaults rather than grow the workspace for tuning
   hipEvent_t ev[2];
   TDO_HIP(hipEventCreate(&ev[0]));
   TDO_HIP(hipEventCreate(&ev[1]));
-  const int cand[3] = {1, 2, 4};
-  int best = 1;
-  float best_ms = 0.f;
   int32_t rc = TDO_OK;
-  for (int rep = 0; rep < 2 && rc == TDO_OK; ++rep)  // first round warms caches and code objects
-    for (int ci = 0; ci < 3 && rc == TDO_OK; ++ci) {
-      np.fwd_wg_per_cu = cand[ci];
-      if (hipEventRecord(ev[0], st) != hipSuccess) { rc = set_error(TDO_EHIP, "hipEventRecord failed"); break; }
-      rc = run_forward(np, w, cfg, E, nullptr, at<float>(c.ws, oxa), at<float>(c.ws, oxb), nullptr, at<float>(c.ws, oz), st);
-      if (rc != TDO_OK) break;
-      if (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) {
-        rc = set_error(TDO_EHIP, "event timing of the forward candidates failed");
-        break;
+  {
+    NetWeights w = weights_at(c.ws, woff);
+    rc = pack_weights(np, params, &w, st);
+    const bool two_shapes = np.bf16 && !np.span;
+    const int waves_c[2] = {8, 4}, wg_c[2] = {1, 2};
+    float best = -1.f;
+    int bw = np.fwd_waves, bg = np.fwd_wg_per_cu;
+    for (int wi = 0; wi < (two_shapes ? 2 : 1) && rc == TDO_OK; ++wi)
+      for (int gi = 0; gi < 2 && rc == TDO_OK; ++gi) {
+        np.fwd_waves = two_shapes ? waves_c[wi] : 4;
+        np.fwd_wg_per_cu = wg_c[gi];
+        const float ms = time_twice(st, ev[0], ev[1], [&]() {
+          return run_forward(np, w, cfg, E, nullptr, at<float>(c.ws, oxa), at<float>(c.ws, oxb), nullptr,
+                             at<float>(c.ws, oz), st);
+        });
+        if (ms < 0.f) rc = set_error(TDO_EHIP, "timing the forward shapes failed");
+        else if (best < 0.f || ms < best) { best = ms; bw = np.fwd_waves; bg = np.fwd_wg_per_cu; }
       }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
-      if (rep == 1 && (ci == 0 || ms < best_ms)) {
-        best_ms = ms;
-        best = cand[ci];
-      }
+    np.fwd_waves = bw;
+    np.fwd_wg_per_cu = bg;
+  }
+  if (rc == TDO_OK && np.bf16 && np.pp.M == 256 && bwd_mlp_bf16_supported(np.pp.d, np.D, np.pp.M)) {
+    const int mlp_c[2] = {8, 4};
+    float best = -1.f;
+    int bm = np.mlp_waves;
+    for (int mi = 0; mi < 2 && rc == TDO_OK; ++mi) {
+      np.mlp_waves = mlp_c[mi];
+      const float ms = time_twice(st, ev[0], ev[1], [&]() {
+        return loss_grad_run(c, np, m, t, params, cfg, B, weights, grad_mode, loss, grad, nullptr, st);
+      });
+      if (ms < 0.f) rc = set_error(TDO_EHIP, "timing the feed-forward backward shapes failed");
+      else if (best < 0.f || ms < best) { best = ms; bm = np.mlp_waves; }
     }
+    np.mlp_waves = bm;
+  }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   TDO_TRY(rc);
-  np.fwd_wg_per_cu = best;
-  c.tune.push_back({key, best});
+  c.tune.push_back({key, np.fwd_wg_per_cu, np.fwd_waves, np.mlp_waves});
+  *added = true;
   return TDO_OK;
 }
 
@@ -161,15 +204,99 @@ extern "C" int32_t tdo_loss_grad_batched(tdo_ctx_t* ctx, const tdo_arch_t* arch,
     TDO_HIP(hipGraphLaunch(gc.exec, stream));
     return TDO_OK;
   }
-  // 3. eager call: autotune the forward grid per distinct shape, then run
+  // 3. eager call: autotune the tile shapes per distinct shape, then run
   if (cap == hipStreamCaptureStatusNone) {
-    for (int32_t p = 0; p < n_problems; ++p) {
-      const int64_t E = std::min<int64_t>(B[p], t[p].chunk);
-      TDO_TRY(tune_forward(c, np[p], params[p], cfg[p], E, stream));
-    }
+    bool added = false;
+    for (int32_t p = 0; p < n_problems; ++p)
+      TDO_TRY(tune_problem(c, np[p], m[p], t[p], params[p], cfg[p], B[p], weights ? weights[p] : nullptr, grad_mode,
+                           loss + p, grad[p], stream, &added));
+    if (added) tune_cache_save(&c);
   }
   TDO_TRY(run_all());
   gc.seen_key = key;
   gc.seen_ws = c.ws;
+  return TDO_OK;
+}
+
+namespace tdo {
+
+void tune_cache_load(Context* c) {
+  const char* path = std::getenv("TDO_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  c->tune_cache = path;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return;
+  std::string text;
+  char buf[4096];
+  size_t k;
+  while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
+  std::fclose(f);
+  size_t pos = 0;
+  while ((pos = text.find("{\"key\":", pos)) != std::string::npos) {
+    unsigned long long key = 0;
+    int wg = 0, fw = 0, mw = 0;
+    if (std::sscanf(text.c_str() + pos, "{\"key\": %llu, \"fwd_wg_per_cu\": %d, \"fwd_waves\": %d, \"mlp_waves\": %d",
+                    &key, &wg, &fw, &mw) == 4 &&
+        (wg == 1 || wg == 2 || wg == 4) && (fw == 4 || fw == 8) && (mw == 4 || mw == 8)) {
+      bool seen = false;
+      for (const TuneEntry& e : c->tune) seen = seen || e.key == key;
+      if (!seen) c->tune.push_back({(uint64_t)key, wg, fw, mw});
+    }
+    pos += 8;
+  }
+}
+
+void tune_cache_save(const Context* c) {
+  if (c->tune_cache.empty()) return;
+  const std::string tmp = c->tune_cache + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return;
+  std::fprintf(f, "{\"tdo_autotune\": 1, \"entries\": [\n");
+  for (size_t i = 0; i < c->tune.size(); ++i) {
+    const TuneEntry& e = c->tune[i];
+    const uint64_t k = e.key;
+    std::fprintf(f,
+                 "  {\"key\": %llu, \"fwd_wg_per_cu\": %d, \"fwd_waves\": %d, \"mlp_waves\": %d, "
+                 "\"shape\": \"n=%d bf16=%d D=%d DH=%d layers=%d mlp=%d\"}%s\n",
+                 (unsigned long long)k, e.fwd_wg_per_cu, e.fwd_waves, e.mlp_waves, (int)(k & 0xff), (int)((k >> 8) & 0xff),
+                 (int)((k >> 16) & 0xff), (int)((k >> 24) & 0xff), (int)((k >> 32) & 0xff), (int)((k >> 40) & 0xffff),
+                 i + 1 < c->tune.size() ? "," : "");
+  }
+  std::fprintf(f, "]}\n");
+  if (std::fclose(f) == 0) std::rename(tmp.c_str(), c->tune_cache.c_str());
+}
+
+}  // namespace tdo
+
+using namespace tdo;
+
+// Tile shapes of one problem tuned now (as the batched call's first call does), kept in the
+// context for every later call with the same shape, and in the cache file if there is one.
+extern "C" int32_t tdo_autotune(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params,
+                                const tdo_model_t* model, const uint64_t* cfg, int64_t B, tdo_prec_t prec,
+                                int32_t grad_mode, double* loss, double* grad, int32_t* shapes, hipStream_t stream) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  Context& c = ctx->c;
+  ModelDev m;
+  NetPlan np;
+  TrainWs t;
+  TDO_TRY(loss_grad_check(c, arch, model, B, prec, grad_mode, &m, &np, &t));
+  TDO_CHECK(params && cfg && loss && grad, TDO_EINVAL, "NULL buffer");
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  TDO_HIP(hipStreamIsCapturing(stream, &cap));
+  TDO_CHECK(cap == hipStreamCaptureStatusNone, TDO_EINVAL, "tuning times kernels: not while the stream is captured");
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
+  bool added = false;
+  TDO_TRY(tune_problem(c, np, m, t, params, cfg, B, nullptr, grad_mode, loss, grad, stream, &added));
+  if (added) tune_cache_save(&c);
+  if (shapes) {
+    shapes[0] = np.fwd_waves;
+    shapes[1] = np.fwd_wg_per_cu;
+    shapes[2] = np.mlp_waves;
+  }
   return TDO_OK;
 }

@@ -4,7 +4,7 @@ set -euo pipefail
 here="$(cd "$(dirname "$0")" && pwd)"
 out="${1:-$here/..}"
 mkdir -p "$here/_build"
-srcs=(api lindblad net_pack net_fwd net_bwd net_bwd_mlp net_bwd_attn train sampler batched observables optim sr noalloc)
+srcs=(api lindblad net_pack net_fwd net_bwd net_bwd_mlp net_bwd_attn train sampler batched observables optim sr noalloc jvp)
 objs=()
 pids=()
 for s in "${srcs[@]}"; do

@@ -79,8 +79,9 @@ struct GraphCache {
 // (chain length, precision, padded width, head width).
 struct TuneEntry {
   uint64_t key;
-  int fwd_wg_per_cu;
+  int fwd_wg_per_cu, fwd_waves, mlp_waves;
 };
+
 
 // Allow a kernel the whole 160 KB LDS of a CU, once per kernel and device per
 // process (a host-side attribute, so later launches, also while a stream is
@@ -97,6 +98,7 @@ struct Context {
   Profiler prof;
   GraphCache graph;
   std::vector<TuneEntry> tune;
+  std::string tune_cache;  // path of the JSON cache of the tuned shapes, or empty
   // count of non-finite parameters (device) and its pinned host copy
   uint32_t* nf_dev = nullptr;
   uint32_t* nf_host = nullptr;
@@ -105,6 +107,11 @@ struct Context {
   hipStream_t ws_stream = nullptr;
   bool ws_recorded = false;
 };
+
+// The autotuned shapes kept in a JSON file (the path in TDO_AUTOTUNE_CACHE): read when a
+// context is created, rewritten when a call tunes a new shape.
+void tune_cache_load(Context* c);
+void tune_cache_save(const Context* c);
 
 // Orders calls that share the context's workspace across streams: the call's stream
 // first waits for the end of the previous call when that ran on another stream, and the

@@ -563,7 +563,7 @@ bool bwd_mlp_bf16_supported(int d, int D, int M) { return d == 64 && D == 64 && 
 
 int32_t launch_bwd_mlp_bf16(const BwdArgs& a, int blocks, hipStream_t st) {
   const bool seeds = a.g_in == nullptr;
-  if (a.M == 256) {
+  if (a.M == 256 && a.mlp_waves != 4) {
     auto go8 = [&](auto kern) -> int32_t {
       TDO_TRY(allow_full_lds((const void*)kern));
       hipLaunchKernelGGL(kern, dim3(blocks), dim3(512), bwd_mlp8_bf16_lds(), st, a);

@@ -69,18 +69,17 @@ __global__ void k_embed_table(const float* __restrict__ params, int d, int D, fl
   }
 }
 
-// Workgroup size: BF16 weights staged in LDS are shared by 8 waves (two per SIMD,
+// Workgroup size NT: BF16 weights staged in LDS are shared by 8 waves (two per SIMD,
 // so that one wave's latencies overlap the other's work) when a wave's registers
-// fit in half a SIMD (one 32-row block per wave); otherwise 4 waves.
-template <class P, bool SPAN>
-constexpr int fwd_threads() { return (P::KPL == 8 && !SPAN) ? 512 : 256; }
+// fit in half a SIMD (one 32-row block per wave), or by 4 waves (one per SIMD, with
+// twice the registers); the choice is autotuned per shape.  Otherwise 4 waves.
 
 // MBC: the feed-forward width in 32-column chunks when fixed at compile time (0: a.M / 32), so
 // that the chunk loop unrolls and one chunk's LDS reads overlap the previous chunk's products.
 // MASKED: some (query, key) pairs of a tile are invalid (several configurations per block, or
 // padding rows); a compile-time choice, so that the unmasked kernel holds no mask registers.
-template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED>
-__global__ void __launch_bounds__((fwd_threads<P, SPAN>())) k_fwd_layer(FwdArgs a) {
+template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED, int NT>
+__global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
   constexpr int NB = D / 32;            // feature blocks
   constexpr int NBR = SPAN ? 2 : 1;     // row blocks per wave
   constexpr int HPB = 32 / DH;          // heads per 32-feature block
@@ -445,17 +444,23 @@ __global__ void k_symmetrise(const int64_t* __restrict__ E_dev, int64_t E_host, 
 }
 
 // ------------------------------------------------------------------ dispatch
-template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED>
-static int32_t launch_layer_m(const FwdArgs& a, int num_cus, hipStream_t st) {
+template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED, int NT>
+static int32_t launch_layer_nt(const FwdArgs& a, int num_cus, hipStream_t st) {
   const size_t wbytes = (P::KPL == 8) ? (size_t)(4 * D * D + 2 * D * a.M) * sizeof(typename P::elem_t) : 0;
-  constexpr int threads = fwd_threads<P, SPAN>();
-  const size_t lds = wbytes + (size_t)(a.M + D) * 4 + (a.first ? 64 * D * 4 : 0) + (threads / 64) * 64 * sizeof(float2);
-  auto kern = k_fwd_layer<P, D, DH, SPAN, MBC, MASKED>;
+  const size_t lds = wbytes + (size_t)(a.M + D) * 4 + (a.first ? 64 * D * 4 : 0) + (NT / 64) * 64 * sizeof(float2);
+  auto kern = k_fwd_layer<P, D, DH, SPAN, MBC, MASKED, NT>;
   TDO_TRY(allow_full_lds((const void*)kern));
   const int blocks = num_cus * a.blocks_per_cu;
-  hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(NT), lds, st, a);
   TDO_HIP(hipGetLastError());
   return TDO_OK;
+}
+
+template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED>
+static int32_t launch_layer_m(const FwdArgs& a, int num_cus, hipStream_t st) {
+  if constexpr (P::KPL == 8 && !SPAN)
+    if (a.waves == 8) return launch_layer_nt<P, D, DH, SPAN, MBC, MASKED, 512>(a, num_cus, st);
+  return launch_layer_nt<P, D, DH, SPAN, MBC, MASKED, 256>(a, num_cus, st);
 }
 
 // the BF16 width-64 kernels with the feed-forward width 4 x 64 fixed at compile time

@@ -26,6 +26,7 @@ struct FwdArgs {
   int n, cpb, d_real, M;
   float score_scale;            // log2(e) / sqrt(d/heads)
   int first, last, masked, blocks_per_cu;
+  int waves;                    // waves per workgroup (4, or 8 for BF16 with n <= 32)
 };
 
 int32_t launch_fwd_layer(const FwdArgs& a, bool bf16, int D, int DH, bool span, int num_cus, hipStream_t st);
@@ -69,6 +70,7 @@ struct BwdArgs {
   int64_t n_entries;
   int n, cpb, span, masked, d_real, M;
   float score_scale, inv_sqrt_dh;
+  int mlp_waves;                // BF16 feed-forward backward at mlp 256: 8 or 4 waves per workgroup
 };
 
 size_t bwd_mlp_lds(int D, int M);

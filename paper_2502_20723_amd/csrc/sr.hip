@@ -15,6 +15,8 @@
 #include <cmath>
 
 #include "common.h"
+#include "netapi.h"
+#include "train.h"
 
 namespace tdo {
 
@@ -174,6 +176,46 @@ __global__ void k_sr_info(const double* __restrict__ sc, double* __restrict__ in
   }
 }
 
+// --- the matrix-free form: S p = J^T (J p) from one forward-mode and one reverse-mode pass
+
+// sc[0..2] = sum w, sum w Re t, sum w Im t over the samples (one workgroup, fixed order).
+__global__ void __launch_bounds__(kT) k_mf_mean(const float* __restrict__ t, const double* __restrict__ w, int64_t B,
+                                                double* __restrict__ sc) {
+  __shared__ double red[kT];
+  double a = 0.0, re = 0.0, im = 0.0;
+  for (int64_t b = threadIdx.x; b < B; b += kT) {
+    const double wb = w ? w[b] : 1.0;
+    a += wb;
+    re += wb * t[2 * b];
+    im += wb * t[2 * b + 1];
+  }
+  a = block_reduce(a, red);
+  re = block_reduce(re, red);
+  im = block_reduce(im, red);
+  if (threadIdx.x == 0) {
+    sc[0] = a;
+    sc[1] = re;
+    sc[2] = im;
+  }
+}
+
+// seed_b = (w_b / W) (t_b - sum w t / W): the reverse-mode seeds of J^T (J p).
+__global__ void k_mf_seeds(const float* __restrict__ t, const double* __restrict__ w, int64_t B,
+                           const double* __restrict__ sc, float* __restrict__ seed) {
+  const double W = sc[0], mr = sc[1] / W, mi = sc[2] / W;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += (int64_t)gridDim.x * blockDim.x) {
+    const double f = (w ? w[b] : 1.0) / W;
+    seed[2 * b] = (float)(f * (t[2 * b] - mr));
+    seed[2 * b + 1] = (float)(f * (t[2 * b + 1] - mi));
+  }
+}
+
+// Ap += lambda p
+__global__ void k_mf_shift(int64_t P, double lambda, const double* __restrict__ p, double* __restrict__ Ap) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < P; k += (int64_t)gridDim.x * blockDim.x)
+    Ap[k] += lambda * p[k];
+}
+
 }  // namespace tdo
 
 using namespace tdo;
@@ -224,6 +266,86 @@ extern "C" int32_t tdo_sr_solve(tdo_ctx_t* ctx, double* jac, int64_t B, int64_t 
     hipLaunchKernelGGL(k_sr_usum, dim3((unsigned)std::min<int64_t>(ceil_div(R, 256), 1024)), dim3(256), 0, stream,
                        up, R, u);
     hipLaunchKernelGGL(k_sr_cols, dim3(gp), dim3(256), 0, stream, jac, R, P, u, p, lambda, Ap);
+    TDO_TRY(dot(p, Ap, sc + 2));
+    hipLaunchKernelGGL(k_sr_step, dim3(gp), dim3(256), 0, stream, P, sc, p, Ap, x, r);
+    TDO_TRY(dot(r, r, sc + 3));
+    hipLaunchKernelGGL(k_sr_dir, dim3(gp), dim3(256), 0, stream, P, sc, r, p);
+    hipLaunchKernelGGL(k_sr_roll, dim3(1), dim3(64), 0, stream, sc);
+    TDO_HIP(hipGetLastError());
+  }
+  if (info) {
+    hipLaunchKernelGGL(k_sr_info, dim3(1), dim3(64), 0, stream, sc, info);
+    TDO_HIP(hipGetLastError());
+  }
+  return TDO_OK;
+}
+
+// S p = Re sum_b w_b conj(dO_b) (dO_b . p) with t_b = O_b . p from the forward-mode pass:
+// sum_b w_b t_b conj... = J^T J p is the reverse-mode product with the seeds w_b (t_b - mean_w t)
+// (the mean term vanishes against the centring of O).
+extern "C" int32_t tdo_sr_solve_matfree(tdo_ctx_t* ctx, const tdo_arch_t* arch, const float* params, int32_t n,
+                                        const uint64_t* cfg, int64_t B, const double* weights, tdo_prec_t prec,
+                                        const double* grad, double lambda, int32_t iters, double* x, double* info,
+                                        hipStream_t stream) {
+  clear_error();
+  TDO_CHECK(ctx != nullptr, TDO_EINVAL, "ctx is NULL");
+  TDO_CHECK(prec == TDO_FP32 || prec == TDO_BF16, TDO_EINVAL, "unknown precision %d", (int)prec);
+  NetPlan npj, npv;
+  TDO_TRY(jvp_check(ctx->c, arch, n, B, &npj));
+  TDO_TRY(net_plan(&ctx->c, arch, n, prec == TDO_BF16, &npv));
+  TDO_CHECK(B >= 1, TDO_EINVAL, "B=%lld < 1", (long long)B);
+  TDO_CHECK(lambda > 0.0 && std::isfinite(lambda), TDO_EINVAL, "diagonal shift lambda=%g must be positive", lambda);
+  TDO_CHECK(iters >= 0, TDO_EINVAL, "iters=%d < 0", iters);
+  TDO_CHECK(params && cfg && grad && x, TDO_EINVAL, "NULL buffer");
+  TDO_HIP(hipSetDevice(ctx->c.device));
+  Context& c = ctx->c;
+  WsOrder order;
+  TDO_TRY(order.begin(&c, stream));
+  TDO_TRY(check_params_finite(&c, params, npj.pp.nparams, stream));
+  const int64_t P = npj.pp.nparams;
+  // CG vectors and scalars, the per-sample tangents and seeds, the forward-mode buffers (at
+  // most a third of the rest of the budget), then the reverse-mode plan in what remains
+  Arena ar;
+  const size_t or_ = ar.take<double>((size_t)P), op = ar.take<double>((size_t)P), oap = ar.take<double>((size_t)P);
+  const size_t osc = ar.take<double>(16), opart = ar.take<double>(kDotParts);
+  const size_t ot = ar.take<float>(2 * (size_t)B), oseed = ar.take<float>(2 * (size_t)B);
+  TDO_CHECK(c.budget > ar.used + 4096, TDO_ENOMEM, "workspace budget %zu too small", c.budget);
+  JvpWs j;
+  TDO_TRY(plan_jvp(npj, B, (c.budget - ar.used) / 3, ar, &j));
+  TrainWs t;
+  TDO_TRY(plan_train_at(c, npv, B, 1, ar.used, c.budget, &t));
+  TDO_TRY(ensure_workspace(&c, t.total));
+  void* ws = c.ws;
+  double *r = at<double>(ws, or_), *p = at<double>(ws, op), *Ap = at<double>(ws, oap), *sc = at<double>(ws, osc);
+  double* part = at<double>(ws, opart);
+  float *tv = at<float>(ws, ot), *seed = at<float>(ws, oseed), *tanf = at<float>(ws, j.tanf);
+  const unsigned gp = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(P, 256), 4096));
+  const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(B, 256), 4096));
+  auto dot = [&](const double* a, const double* b, double* out) -> int32_t {
+    hipLaunchKernelGGL(k_sr_dot, dim3(kDotParts), dim3(kT), 0, stream, a, b, P, part);
+    hipLaunchKernelGGL(k_sr_dot_fin, dim3(1), dim3(kT), 0, stream, part, out);
+    TDO_HIP(hipGetLastError());
+    return TDO_OK;
+  };
+  {  // the reverse-mode weight fragments, packed once
+    NetWeights w = weights_at(ws, t.woff);
+    TDO_TRY(pack_weights(npv, params, &w, stream));
+    TDO_TRY(launch_pack_backward(npv.pp, params, npv.bf16, at<char>(ws, t.wback), stream));
+  }
+  // sc: [1] rs, [2] p.Ap, [3] rs_new, [4] g.g, [8..10] weight sum and weighted tangent sums
+  hipLaunchKernelGGL(k_sr_init, dim3(gp), dim3(256), 0, stream, grad, P, x, r, p);
+  TDO_HIP(hipGetLastError());
+  TDO_TRY(dot(grad, grad, sc + 1));
+  TDO_TRY(dot(grad, grad, sc + 4));
+  for (int32_t it = 0; it < iters; ++it) {
+    TDO_TRY(jvp_tangent_f32(p, P, tanf, stream));
+    TDO_TRY(run_jvp(npj, ws, j, params, cfg, B, tv, stream));
+    hipLaunchKernelGGL(k_mf_mean, dim3(1), dim3(kT), 0, stream, tv, weights, B, sc + 8);
+    hipLaunchKernelGGL(k_mf_seeds, dim3(gb), dim3(256), 0, stream, tv, weights, B, sc + 8, seed);
+    TDO_HIP(hipGetLastError());
+    TDO_TRY(vjp_run(c, npv, t, params, cfg, B, seed, Ap, true, stream));
+    hipLaunchKernelGGL(k_mf_shift, dim3(gp), dim3(256), 0, stream, P, lambda, p, Ap);
+    TDO_HIP(hipGetLastError());
     TDO_TRY(dot(p, Ap, sc + 2));
     hipLaunchKernelGGL(k_sr_step, dim3(gp), dim3(256), 0, stream, P, sc, p, Ap, x, r);
     TDO_TRY(dot(r, r, sc + 3));

@@ -15,6 +15,8 @@ struct NetPlan {
   float score_scale;
   Profiler* prof;
   int fwd_wg_per_cu;  // workgroups per CU of the forward layer kernel (autotuned, default 1)
+  int fwd_waves;      // waves per workgroup of the forward layer kernel: 8 (BF16, n <= 32) or 4 (autotuned)
+  int mlp_waves;      // waves per workgroup of the BF16 feed-forward backward at mlp 256: 8 or 4 (autotuned)
 };
 
 inline uint64_t tune_key(const NetPlan& np) {
@@ -53,6 +55,12 @@ struct TrainWs {
 
 struct ModelDev;
 int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, TrainWs* t);
+// The same layout starting at byte offset base of the workspace, within cap bytes in all; allocates nothing.
+int32_t plan_train_at(const Context& c, const NetPlan& np, int64_t B, int nslots, size_t base, size_t cap,
+                      TrainWs* t);
+// tdo_log_rho_vjp's launch sequence on a planned workspace (packed: weight fragments already packed).
+int32_t vjp_run(Context& c, const NetPlan& np, const TrainWs& t, const float* params, const uint64_t* cfg, int64_t B,
+                const float* seed, double* grad, bool packed, hipStream_t stream);
 // Validation and workspace plan of one loss/gradient evaluation (grows the workspace).
 int32_t loss_grad_check(const Context& c, const tdo_arch_t* arch, const tdo_model_t* model, int64_t B, tdo_prec_t prec,
                         int32_t grad_mode, ModelDev* m, NetPlan* np, TrainWs* t);
@@ -62,6 +70,19 @@ int32_t loss_grad_run(Context& c, const NetPlan& np, const ModelDev& m, const Tr
                       double* grad, float* lloc_out, hipStream_t stream);
 
 int32_t net_plan(const Context* c, const tdo_arch_t* arch, int n, bool bf16, NetPlan* np);
+
+// Forward-mode pass (jvp.hip): buffers for chunks of ec configurations, laid out by plan_jvp
+// from ar.used on within max_bytes (the FP32 tangent of the parameters first).
+struct JvpWs {
+  int64_t ec = 0;
+  size_t tanf, T, Td, X, Xd, Y, Yd, Q, K, V, Qd, Kd, Vd, O, Od, H, Hd, z, zd;
+};
+int32_t plan_jvp(const NetPlan& np, int64_t B, size_t max_bytes, Arena& ar, JvpWs* j);
+// out[e] (re, im) = d log rho(cfg[e]) along the tangent held at ws + j.tanf (FP32).
+int32_t run_jvp(const NetPlan& np, void* ws, const JvpWs& j, const float* params, const uint64_t* cfg, int64_t B,
+                float* out, hipStream_t st);
+int32_t jvp_check(const Context& c, const tdo_arch_t* arch, int32_t n, int64_t B, NetPlan* np);
+int32_t jvp_tangent_f32(const double* p, int64_t P, float* out, hipStream_t st);
 int64_t blocks_for(const NetPlan& np, int64_t E);
 int32_t pack_weights(const NetPlan& np, const float* params, NetWeights* w, hipStream_t st);
 void carve_weights(const NetPlan& np, Arena& ar, size_t* offs);

@@ -158,6 +158,7 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
     a.M = M;
     a.score_scale = np.score_scale;
     a.inv_sqrt_dh = (float)(1.0 / std::sqrt((double)np.DH));
+    a.mlp_waves = np.mlp_waves;
     // feed-forward sub-layer: gradient in ga (or from the seeds), out to gb
     a.g_in = (l == L - 1) ? nullptr : bb.ga;
     a.seeds = (l == L - 1) ? dF : nullptr;
@@ -203,11 +204,13 @@ static int32_t finish_backward(const NetPlan& np, const BwdBufs& bb, const float
 }
 
 
-int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, TrainWs* t) {
+int32_t plan_train_at(const Context& c, const NetPlan& np, int64_t B, int nslots, size_t base, size_t cap,
+                      TrainWs* t) {
   const PackPlan& pp = np.pp;
   TDO_CHECK(bwd_mlp_lds(np.D, pp.M) <= 160 * 1024, TDO_EUNSUPPORTED,
             "backward of width %d with mlp %d exceeds the LDS of a workgroup", np.D, pp.M);
   Arena ar;
+  ar.used = (base + 255) & ~size_t(255);
   carve_weights(np, ar, t->woff);
   t->wback = ar.take<char>((size_t)pp.layer_elems * pp.layers * np.elem);
   t->gA = ar.take<double>(pp.nparams);
@@ -234,10 +237,10 @@ int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, T
                            (keep_lse ? (double)pp.layers * 32 * (np.D / np.DH) * 4 : 0.0);
   const double per_entry = blocks_per_entry * per_block + 80.0;
   const double per_sample = nslots * per_entry + 32.0;
-  TDO_CHECK(c.budget > fixed + per_sample + 8 * per_block, TDO_ENOMEM,
-            "workspace budget %zu bytes cannot hold one sample (%.0f bytes) and the fixed part (%zu bytes)", c.budget,
+  TDO_CHECK(cap > fixed + per_sample + 8 * per_block, TDO_ENOMEM,
+            "workspace budget %zu bytes cannot hold one sample (%.0f bytes) and the fixed part (%zu bytes)", cap,
             per_sample, fixed);
-  int64_t chunk = (int64_t)((double)(c.budget - fixed - 8 * per_block) / per_sample);
+  int64_t chunk = (int64_t)((double)(cap - fixed - 8 * per_block) / per_sample);
   chunk = std::max<int64_t>(1, std::min(chunk, B));
   t->chunk = chunk;
   t->emax = chunk * nslots;
@@ -261,8 +264,42 @@ int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, T
   t->lse_layer = keep_lse ? (size_t)t->nblk * 32 * (np.D / np.DH) : 0;
   t->slse = ar.take<float>(t->lse_layer * pp.layers + 64);
   t->total = ar.used;
-  TDO_TRY(ensure_workspace(const_cast<Context*>(&c), ar.used));
   return TDO_OK;
+}
+
+int32_t plan_train(const Context& c, const NetPlan& np, int64_t B, int nslots, TrainWs* t) {
+  TDO_TRY(plan_train_at(c, np, B, nslots, 0, c.budget, t));
+  return ensure_workspace(const_cast<Context*>(&c), t->total);
+}
+
+// The launch sequence of tdo_log_rho_vjp on a planned workspace: grad = sum_b seed_b . d log rho(x_b).
+// With packed set, the forward and transposed weight fragments are taken as already packed.
+int32_t vjp_run(Context& c, const NetPlan& np, const TrainWs& t, const float* params, const uint64_t* cfg, int64_t B,
+                const float* seed, double* grad, bool packed, hipStream_t stream) {
+  void* ws = c.ws;
+  NetWeights w = weights_at(ws, t.woff);
+  if (!packed) {
+    TDO_TRY(pack_weights(np, params, &w, stream));
+    TDO_TRY(launch_pack_backward(np.pp, params, np.bf16, at<char>(ws, t.wback), stream));
+  } else {
+    w.head_w = params + np.pp.off_head_w;
+    w.head_b = params + np.pp.off_head_b;
+  }
+  TDO_TRY(fill(grad, np.pp.nparams, 0.0, stream));
+  TDO_TRY(fill(at<double>(ws, t.dT_acc), 64LL * np.D, 0.0, stream));
+  BwdBufs bb{at<char>(ws, t.wback), at<float>(ws, t.xa), at<float>(ws, t.xb), at<float>(ws, t.partial), c.num_cus,
+             at<double>(ws, t.mlp_acc), at<double>(ws, t.attn_acc), at<double>(ws, t.dT_acc)};
+  Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes,
+           t.lse_layer ? at<float>(ws, t.slse) : nullptr, t.lse_layer};
+  for (int64_t e0 = 0; e0 < B; e0 += t.chunk) {
+    const int64_t E = std::min(t.chunk, B - e0);
+    const uint64_t* ec = cfg + 2 * e0;
+    TDO_TRY(run_forward(np, w, ec, E, nullptr, at<float>(ws, t.xa), at<float>(ws, t.xb), &sv, at<float>(ws, t.z), stream));
+    hipLaunchKernelGGL(k_seeds_vjp, dim3(256), dim3(256), 0, stream, seed + 2 * e0, at<float>(ws, t.z), E, at<float>(ws, t.dF));
+    TDO_HIP(hipGetLastError());
+    TDO_TRY(run_backward(np, w, bb, params, ec, E, nullptr, sv, at<float>(ws, t.dF), grad, stream));
+  }
+  return finish_backward(np, bb, params, grad, stream);
 }
 
 }  // namespace tdo
@@ -286,26 +323,7 @@ extern "C" int32_t tdo_log_rho_vjp(tdo_ctx_t* ctx, const tdo_arch_t* arch, const
   TDO_TRY(check_params_finite(&c, params, np.pp.nparams, stream));
   TrainWs t;
   TDO_TRY(plan_train(c, np, std::max<int64_t>(B, 1), 1, &t));
-  void* ws = c.ws;
-  NetWeights w = weights_at(ws, t.woff);
-  TDO_TRY(pack_weights(np, params, &w, stream));
-  TDO_TRY(launch_pack_backward(np.pp, params, np.bf16, at<char>(ws, t.wback), stream));
-  TDO_TRY(fill(grad, np.pp.nparams, 0.0, stream));
-  TDO_TRY(fill(at<double>(ws, t.dT_acc), 64LL * np.D, 0.0, stream));
-  BwdBufs bb{at<char>(ws, t.wback), at<float>(ws, t.xa), at<float>(ws, t.xb), at<float>(ws, t.partial), c.num_cus,
-             at<double>(ws, t.mlp_acc), at<double>(ws, t.attn_acc), at<double>(ws, t.dT_acc)};
-  Saves sv{at<char>(ws, t.sx), at<char>(ws, t.smid), at<char>(ws, t.slast), t.layer_bytes,
-           t.lse_layer ? at<float>(ws, t.slse) : nullptr, t.lse_layer};
-  for (int64_t e0 = 0; e0 < B; e0 += t.chunk) {
-    const int64_t E = std::min(t.chunk, B - e0);
-    const uint64_t* ec = cfg + 2 * e0;
-    TDO_TRY(run_forward(np, w, ec, E, nullptr, at<float>(ws, t.xa), at<float>(ws, t.xb), &sv, at<float>(ws, t.z), stream));
-    hipLaunchKernelGGL(k_seeds_vjp, dim3(256), dim3(256), 0, stream, seed + 2 * e0, at<float>(ws, t.z), E, at<float>(ws, t.dF));
-    TDO_HIP(hipGetLastError());
-    TDO_TRY(run_backward(np, w, bb, params, ec, E, nullptr, sv, at<float>(ws, t.dF), grad, stream));
-  }
-  TDO_TRY(finish_backward(np, bb, params, grad, stream));
-  return TDO_OK;
+  return vjp_run(c, np, t, params, cfg, B, seed, grad, false, stream);
 }
 
 // Per-sample log-derivatives: per configuration one forward, then one backward

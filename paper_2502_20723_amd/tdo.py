@@ -23,7 +23,7 @@ EXPORTS = ("tdo_ctx_create", "tdo_ctx_destroy", "tdo_num_params", "tdo_last_erro
            "tdo_profile_read", "tdo_connected", "tdo_local_lindbladian", "tdo_log_rho", "tdo_log_rho_vjp",
            "tdo_loss_grad", "tdo_loss_grad_batched", "tdo_sample", "tdo_sample_diag", "tdo_observables",
            "tdo_purity", "tdo_lr_schedule", "tdo_sgd_step", "tdo_adam_step", "tdo_log_rho_jacobian",
-           "tdo_sr_solve", "tdo_log_rho_noalloc")
+           "tdo_sr_solve", "tdo_log_rho_noalloc", "tdo_log_rho_jvp", "tdo_sr_solve_matfree", "tdo_autotune")
 
 
 class ArchT(ctypes.Structure):
@@ -81,6 +81,11 @@ def lib() -> ctypes.CDLL:
         L.tdo_adam_step.argtypes = [i64, vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, vp]
         L.tdo_log_rho_jacobian.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, i32, vp, vp]
         L.tdo_sr_solve.argtypes = [vp, vp, i64, i64, vp, vp, dbl, i32, vp, vp, vp]
+        L.tdo_autotune.argtypes = [vp, ctypes.POINTER(ArchT), vp, ctypes.POINTER(ModelT), vp, i64, i32, i32, vp, vp,
+                                   ctypes.POINTER(ctypes.c_int32), vp]
+        L.tdo_log_rho_jvp.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, vp, vp, vp]
+        L.tdo_sr_solve_matfree.argtypes = [vp, ctypes.POINTER(ArchT), vp, i32, vp, i64, vp, i32, vp, dbl, i32, vp, vp,
+                                           vp]
         for name in EXPORTS:
             if name not in ("tdo_last_error", "tdo_num_params", "tdo_ctx_create", "tdo_ctx_destroy",
                             "tdo_lr_schedule"):
@@ -263,6 +268,20 @@ class Ctx:
                                    _ptr(grad), _ptr(lloc), _stream()))
         return loss, grad, lloc
 
+    def autotune(self, arch: dict, params, model: dict, cfg, prec="bf16", mode="B"):
+        """Tune the tile shapes of this problem's shape; returns (forward waves, forward
+        workgroups per CU, feed-forward backward waves)."""
+        B, P = cfg.shape[0], num_params(arch)
+        _dev(params, torch.float32, (P,), "params")
+        _dev(cfg, torch.uint64, (B, 2), "cfg")
+        loss = torch.empty((1,), dtype=torch.float64, device=cfg.device)
+        grad = torch.empty((P,), dtype=torch.float64, device=cfg.device)
+        shapes = (ctypes.c_int32 * 3)()
+        _check(lib().tdo_autotune(self.h, ctypes.byref(arch_t(arch)), _ptr(params), ctypes.byref(model_t(model)),
+                                  _ptr(cfg), B, PREC[prec], {"B": 0, "A": 1}[mode], _ptr(loss), _ptr(grad), shapes,
+                                  _stream()))
+        return tuple(int(v) for v in shapes)
+
     def loss_grad_batched(self, arch: dict, params: list, models: list, cfgs: list, weights=None, prec="fp32",
                           mode="B", out=None):
         """Loss and gradient of several problems in one call.  out = (loss [n] float64
@@ -329,6 +348,34 @@ class Ctx:
         info = torch.empty((2,), dtype=torch.float64, device=jac.device)
         _check(lib().tdo_sr_solve(self.h, _ptr(jac), B, P, _ptr(weights), _ptr(grad), lam, iters, _ptr(x),
                                   _ptr(info), _stream()))
+        return x, info
+
+    def log_rho_jvp(self, arch: dict, params, n: int, cfg, tangent):
+        """d log rho(x_b) along tangent (device float64 [P]) as float32 [B, 2] (re, im)."""
+        B, P = cfg.shape[0], num_params(arch)
+        _dev(params, torch.float32, (P,), "params")
+        _dev(cfg, torch.uint64, (B, 2), "cfg")
+        _dev(tangent, torch.float64, (P,), "tangent")
+        out = torch.empty((B, 2), dtype=torch.float32, device=cfg.device)
+        _check(lib().tdo_log_rho_jvp(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(cfg), B, _ptr(tangent),
+                                     _ptr(out), _stream()))
+        return out
+
+    def sr_solve_matfree(self, arch: dict, params, n: int, cfg, grad, lam: float, iters: int, weights=None,
+                         prec="fp32"):
+        """x = (S + lam I)^-1 grad with S applied as J^T (J p) (no Jacobian stored).
+        Returns (x, info [rel. residual, |g|])."""
+        B, P = cfg.shape[0], num_params(arch)
+        _dev(params, torch.float32, (P,), "params")
+        _dev(cfg, torch.uint64, (B, 2), "cfg")
+        _dev(grad, torch.float64, (P,), "grad")
+        if weights is not None:
+            _dev(weights, torch.float64, (B,), "weights")
+        x = torch.empty((P,), dtype=torch.float64, device=cfg.device)
+        info = torch.empty((2,), dtype=torch.float64, device=cfg.device)
+        _check(lib().tdo_sr_solve_matfree(self.h, ctypes.byref(arch_t(arch)), _ptr(params), n, _ptr(cfg), B,
+                                          _ptr(weights), PREC[prec], _ptr(grad), lam, iters, _ptr(x), _ptr(info),
+                                          _stream()))
         return x, info
 
     def sample_diag(self, arch: dict, params, n: int, state, state_lr, seed: int, counter: int, sweeps: int,

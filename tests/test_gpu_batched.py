@@ -59,17 +59,20 @@ REPEAT_TOL = {"fp32": 1e-5, "bf16": 0.0}
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_equals_single_problem_calls_and_replays(gpu, prec):
     """The batched call (eager, then recorded, then replayed) gives the results of
-    separate tdo_loss_grad calls; a replay reads the current contents of its inputs."""
+    separate tdo_loss_grad calls on the same context, which use the tile shapes the
+    first batched call tuned; a replay reads the current contents of its inputs."""
     models, params, cfgs = problems(8, 64, 77)
     ctx = gpu.Ctx(0)
     pt = [cuda(p) for p in params]
     ct = [cuda(c) for c in cfgs]
-    ref = [ctx.loss_grad(ARCH, pt[i], models[i], ct[i], None, prec, "B") for i in range(8)]
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
         out = (torch.empty(8, dtype=torch.float64, device="cuda"),
                [torch.empty(synth.num_params(ARCH), dtype=torch.float64, device="cuda") for _ in range(8)])
+        ctx.loss_grad_batched(ARCH, pt, models, ct, None, prec, "B", out=out)  # tunes the shapes
+        ref = [ctx.loss_grad(ARCH, pt[i], models[i], ct[i], None, prec, "B") for i in range(8)]
+        s.synchronize()
         for call in range(3):  # eager, recorded, replayed
             loss, grads = ctx.loss_grad_batched(ARCH, pt, models, ct, None, prec, "B", out=out)
             s.synchronize()
@@ -125,3 +128,49 @@ def test_validation_before_launch(gpu):
         ctx.loss_grad_batched(ARCH, [cuda(p) for p in params], models, [cuda(c) for c in cfgs])
     loss, grads = ctx.loss_grad_batched(ARCH, [], [], [])
     assert loss.shape == (0,) and grads == []
+
+
+def test_autotune_cache_file(gpu, tmp_path, monkeypatch):
+    """TDO_AUTOTUNE_CACHE: the first context's batched call tunes the tile shapes and
+    writes them to the file (one entry per distinct shape); a second context reads them,
+    so its results equal the first context's bit for bit (BF16)."""
+    import json
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("TDO_AUTOTUNE_CACHE", str(path))
+    models, params, cfgs = problems(6, 64, 78)
+    pt = [cuda(p) for p in params]
+    ct = [cuda(c) for c in cfgs]
+    ctx1 = gpu.Ctx(0)
+    l1, g1 = ctx1.loss_grad_batched(ARCH, pt, models, ct, None, "bf16", "B")
+    torch.cuda.synchronize()
+    doc = json.loads(path.read_text())
+    shapes = {(m["n"]) for m in models}
+    print(f"cache: {len(doc['entries'])} entries for {len(shapes)} chain lengths: "
+          + "; ".join(f"{e['shape']}: fwd {e['fwd_waves']} waves x {e['fwd_wg_per_cu']}/CU, mlp {e['mlp_waves']} waves"
+                      for e in doc["entries"]))
+    assert len(doc["entries"]) == len(shapes)
+    for e in doc["entries"]:
+        assert e["fwd_waves"] in (4, 8) and e["mlp_waves"] in (4, 8) and e["fwd_wg_per_cu"] in (1, 2)
+    ctx2 = gpu.Ctx(0)
+    ref = [ctx2.loss_grad(ARCH, pt[i], models[i], ct[i], None, "bf16", "B") for i in range(6)]
+    torch.cuda.synchronize()
+    for i in range(6):
+        assert float(ref[i][0][0]) == float(l1[i])
+        assert torch.equal(ref[i][1], g1[i])
+
+
+def test_autotune_entry_point(gpu, tmp_path, monkeypatch):
+    """tdo_autotune on one problem returns shapes from the candidate sets, adds the shape to
+    the cache file, and later calls of that shape give the oracle's loss."""
+    import json
+    path = tmp_path / "tune1.json"
+    monkeypatch.setenv("TDO_AUTOTUNE_CACHE", str(path))
+    models, params, cfgs = problems(1, 48, 79)
+    ctx = gpu.Ctx(0)
+    shapes = ctx.autotune(ARCH, cuda(params[0]), models[0], cuda(cfgs[0]), "bf16", "B")
+    print(f"tuned shapes n={models[0]['n']}: {shapes}")
+    assert shapes[0] in (4, 8) and shapes[1] in (1, 2) and shapes[2] in (4, 8)
+    assert len(json.loads(path.read_text())["entries"]) == 1
+    loss, _, _ = ctx.loss_grad(ARCH, cuda(params[0]), models[0], cuda(cfgs[0]), None, "bf16", "B")
+    F = vmc.loss(params[0].astype(np.float64), oa.Arch(**ARCH), ol.Model(**models[0]), cfgs[0])[0]
+    assert abs(float(loss[0]) - F) / F < 2e-2
