@@ -136,3 +136,32 @@ def test_nonfinite_params_rejected(gpu, bad):
     params[len(params) // 3] = 0.01
     ok = ctx.log_rho(ARCH, cuda(params), n, cfg)
     assert bool(torch.isfinite(ok).all())
+
+
+def test_one_context_on_two_streams(gpu):
+    """Calls on one context alternating between two streams, with no synchronisation by the
+    caller between them, give the results of the same calls made on one stream: a call on
+    another stream than the previous call waits for it before touching the shared
+    workspace (each call's parameter check waits only on its own stream).  Width 64, whose
+    BF16 kernels sum in a fixed order, so equal means bit-identical."""
+    n = MODEL["n"]
+    arch = synth.WORKLOADS["ising_n32"]["arch"]
+    ctx = gpu.Ctx(0)
+    p = [cuda(synth.params(arch, 11 + i, "mid")) for i in range(4)]
+    c = [cuda(synth.configs(n, 3000, 21 + i)) for i in range(4)]
+    ref = []
+    for i in range(4):
+        loss, grad, _ = ctx.loss_grad(arch, p[i], MODEL, c[i], None, "bf16", "B")
+        ref.append((loss.clone(), grad.clone()))
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    out = []
+    for i in range(4):
+        with torch.cuda.stream(s1 if i % 2 == 0 else s2):
+            out.append(ctx.loss_grad(arch, p[i], MODEL, c[i], None, "bf16", "B")[:2])
+    torch.cuda.synchronize()
+    for i in range(4):
+        assert torch.equal(out[i][0], ref[i][0]), i
+        assert torch.equal(out[i][1], ref[i][1]), i

@@ -39,3 +39,29 @@ def test_noalloc_matches_log_rho_twice(gpu, prec):
               f"free memory change {free1 - free0} bytes")
         assert err < TOL[prec]
         assert free1 == free0
+
+
+def test_noalloc_under_graph_capture(gpu):
+    """The case the entry point is for: captured into a graph (torch.cuda.graph) and replayed
+    three times, with the inputs changed in place and eager work between the replays; every
+    replay equals tdo_log_rho on the current inputs."""
+    arch = synth.WORKLOADS["ising_n32"]["arch"]
+    n, B = 32, 2500
+    params = torch.from_numpy(synth.params(arch, 93, "mid")).cuda()
+    cfg = torch.from_numpy(synth.configs(n, B, 94)).cuda()
+    out = torch.zeros((B, 2), dtype=torch.float32, device="cuda")
+    ctx = gpu.Ctx(0)
+    ctx.log_rho_noalloc(arch, params, n, cfg, out, "bf16")   # warm the kernels before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.log_rho_noalloc(arch, params, n, cfg, out, "bf16")
+    for rep in range(3):
+        cfg.copy_(torch.from_numpy(synth.configs(n, B, 95 + rep)).cuda())
+        params.mul_(0.9)
+        g.replay()
+        torch.cuda.synchronize()
+        ref = ctx.log_rho(arch, params, n, cfg, "bf16")
+        torch.cuda.synchronize()
+        print(f"replay {rep}: identical to tdo_log_rho {bool(torch.equal(out, ref))}")
+        assert torch.equal(out, ref), rep
