@@ -61,6 +61,14 @@ struct PBF16 {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
   __device__ static __forceinline__ op_t op(const f32x16& v, int s) { return cvt8(v, s); }
+  // Operand s of relu(v).  Rounding to BF16 keeps the sign (a negative value rounds to a
+  // negative value or -0), so the ReLU of the rounded pair is a signed 16-bit maximum with
+  // 0 on the packed bits: one instruction per two values, the same bits as rounding relu(v).
+  __device__ static __forceinline__ op_t relu_op(const f32x16& v, int s) {
+    typedef short s16x8 __attribute__((ext_vector_type(8)));
+    const s16x8 t = __builtin_bit_cast(s16x8, cvt8(v, s));
+    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(t, (s16x8){}));
+  }
   // Score operand of one head: its DH features of a 32-feature result tile
   // (values [DH/2*j, DH/2*j + DH/2) of each lane), packed once and reused.
   template <int DH>
@@ -98,6 +106,7 @@ struct PF32 {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
   }
   __device__ static __forceinline__ op_t op(const f32x16& v, int s) { return v[s]; }
+  __device__ static __forceinline__ op_t relu_op(const f32x16& v, int s);
   template <int DH>
   struct SOp {
     float v[DH / 2];
@@ -217,7 +226,11 @@ __device__ __forceinline__ void barrier_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Exact ReLU of the feed-forward sub-layer.
-__device__ __forceinline__ float relu(float x) { return x > 0.f ? x : 0.f; }
+// Exact ReLU of the feed-forward sub-layer as a signed integer maximum of the bits with 0:
+// one instruction (a float maximum first quiets its inputs, a second instruction).  A
+// negative value or -0 gives +0; it differs from x > 0 ? x : 0 only for a NaN input, which
+// it passes on instead of replacing by 0.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+__device__ __forceinline__ float PF32::relu_op(const f32x16& v, int s) { return relu(v[s]); }
 
 }  // namespace tdo

@@ -145,8 +145,29 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
       okbits[qb][kb] = bits;
     }
 
-  for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; tile < ntiles;
-       tile += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+  // x of a layer after the first, for the wave's next tile: loaded one tile ahead (one row
+  // block per tile; the two of a spanning tile would not fit in the registers), so that the
+  // latency of the loads overlaps the current tile's work
+  const int64_t tstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+  f32x16 xnext[NBR][NB];
+  auto fetch_x = [&](int64_t tl) {
+    if (a.first || tl >= ntiles) return;
+#pragma unroll
+    for (int rb = 0; rb < NBR; ++rb)
+#pragma unroll
+      for (int ob = 0; ob < NB; ++ob) {
+        const float4* src = reinterpret_cast<const float4*>(a.x_in + (((tl * NBR + rb) * NB + ob) * 64 + lane) * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 v = src[q];
+          xnext[rb][ob][4 * q + 0] = v.x; xnext[rb][ob][4 * q + 1] = v.y;
+          xnext[rb][ob][4 * q + 2] = v.z; xnext[rb][ob][4 * q + 3] = v.w;
+        }
+      }
+  };
+  if (!SPAN) fetch_x((int64_t)blockIdx.x * (blockDim.x >> 6) + wave);
+
+  for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave; tile < ntiles; tile += tstride) {
     const int pass = (int)(tile & 1);
     // first entry of the tile and the slot/validity of this lane's rows
     const int64_t e0 = SPAN ? (tile >> 1) : (tile >> 1) * cpb;
@@ -185,19 +206,13 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
         }
       }
     } else {
+      if (SPAN) fetch_x(tile);
 #pragma unroll
       for (int rb = 0; rb < NBR; ++rb)
 #pragma unroll
-        for (int ob = 0; ob < NB; ++ob) {
-          const float4* src = reinterpret_cast<const float4*>(a.x_in + (((gblk0 + rb) * NB + ob) * 64 + lane) * 16);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float4 v = src[q];
-            x[rb][ob][4 * q + 0] = v.x; x[rb][ob][4 * q + 1] = v.y;
-            x[rb][ob][4 * q + 2] = v.z; x[rb][ob][4 * q + 3] = v.w;
-          }
-        }
+        for (int ob = 0; ob < NB; ++ob) x[rb][ob] = xnext[rb][ob];
     }
+    if (!SPAN) fetch_x(tile + tstride);
     auto save = [&](void* dst, const f32x16 (&v)[NBR][NB]) {
       save_t* s = reinterpret_cast<save_t*>(dst);
 #pragma unroll
@@ -342,29 +357,52 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
       for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
         for (int s = 0; s < ST; ++s) xo[rb][ib][s] = P::op(x[rb][ib], s);
-#pragma unroll
-    for (int c = 0; c < MB; ++c) {
-      // the products accumulate onto b1 (values r = 4q .. 4q+3 hold 4 consecutive hidden units)
-      f32x16 bias;
+    // pre-activations of 32-unit chunk c: the products accumulate onto b1 (values
+    // r = 4q .. 4q+3 hold 4 consecutive hidden units)
+    auto ffn_pre = [&](int c, int rb) {
+      f32x16 u;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float4 b = *reinterpret_cast<const float4*>(b1s + 32 * c + 8 * q + 4 * h);
-        bias[4 * q] = b.x; bias[4 * q + 1] = b.y; bias[4 * q + 2] = b.z; bias[4 * q + 3] = b.w;
+        u[4 * q] = b.x; u[4 * q + 1] = b.y; u[4 * q + 2] = b.z; u[4 * q + 3] = b.w;
       }
 #pragma unroll
-      for (int rb = 0; rb < NBR; ++rb) {
-        f32x16 u = bias;
+      for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
-        for (int ib = 0; ib < NB; ++ib)
+        for (int s = 0; s < ST; ++s) u = P::mma(ld_frag<P>(W1, (c * NB + ib) * ST + s, lane), xo[rb][ib][s], u);
+      return u;
+    };
+    // One row block: software-pipelined over the chunks, chunk c+1's pre-activation products
+    // issued before chunk c's ReLU and conversions, which then overlap them on the vector ALU
+    // (two row blocks: chunk by chunk, a second chunk in flight would not fit in the
+    // registers).  Each accumulator of x takes the chunks in order either way.
+    if constexpr (SPAN) {
 #pragma unroll
-          for (int s = 0; s < ST; ++s) u = P::mma(ld_frag<P>(W1, (c * NB + ib) * ST + s, lane), xo[rb][ib][s], u);
+      for (int c = 0; c < MB; ++c)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) u[r] = relu(u[r]);
+        for (int rb = 0; rb < NBR; ++rb) {
+          const f32x16 u = ffn_pre(c, rb);
+#pragma unroll
+          for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+            for (int s = 0; s < ST; ++s)
+              x[rb][ob] = P::mma(ld_frag<P>(W2, (ob * MB + c) * ST + s, lane), P::relu_op(u, s), x[rb][ob]);
+        }
+    } else {
+      constexpr int rb = 0;
+      f32x16 un = ffn_pre(0, rb);
+#pragma unroll
+      for (int c = 0; c < MB; ++c) {
+        const f32x16 u = un;
+        if (c + 1 < MB) un = ffn_pre(c + 1, rb);
+        op_t uo[ST];
+#pragma unroll
+        for (int s = 0; s < ST; ++s) uo[s] = P::relu_op(u, s);
 #pragma unroll
         for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
           for (int s = 0; s < ST; ++s)
-            x[rb][ob] = P::mma(ld_frag<P>(W2, (ob * MB + c) * ST + s, lane), P::op(u, s), x[rb][ob]);
+            x[rb][ob] = P::mma(ld_frag<P>(W2, (ob * MB + c) * ST + s, lane), uo[s], x[rb][ob]);
       }
     }
 #pragma unroll
