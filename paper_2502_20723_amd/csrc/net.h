@@ -208,14 +208,14 @@ __device__ __forceinline__ bf16x8 rld8(__amdgpu_buffer_rsrc_t r, int voff, int s
 __device__ __forceinline__ float2 rld2(__amdgpu_buffer_rsrc_t r, int voff) {
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
 }
-__device__ __forceinline__ float4 rld4(__amdgpu_buffer_rsrc_t r, int voff) {
-  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, 0, 0));
+__device__ __forceinline__ float4 rld4(__amdgpu_buffer_rsrc_t r, int voff, int soff = 0) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 __device__ __forceinline__ void rst2(__amdgpu_buffer_rsrc_t r, int voff, float2 v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(int __attribute__((ext_vector_type(2))), v), r, voff, 0, 0);
 }
-__device__ __forceinline__ void rst4(__amdgpu_buffer_rsrc_t r, int voff, float4 v) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, voff, 0, 0);
+__device__ __forceinline__ void rst4(__amdgpu_buffer_rsrc_t r, int voff, float4 v, int soff = 0) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, voff, soff, 0);
 }
 
 // Workgroup barrier that orders LDS accesses only: global loads (a prefetch of the next

@@ -13,25 +13,30 @@
 // (attention features [32 (w/4), 32 (w/4) + 32)) of block w % 4 of the tile,
 // then owns rows [32 (w/4), 32 (w/4) + 32) of one weight gradient (w % 4 = 0..3:
 // Wq, Wk, Wv, W_O) accumulated in registers for the whole launch.  The two waves
-// of a block add their dx terms in turn through LDS: head block 0 leaves g + its
-// terms in the exchange area before the workgroup barrier, head block 1 adds its
+// of a block add their dx terms in turn through LDS: head block 0 leaves its terms
+// in the exchange area before the workgroup barrier, head block 1 adds g and its own
 // terms after it and writes dx.
 //
 // Block phase (one wave per head block).  Every contraction over keys or queries needs its
 // operands with lanes enumerating features and values enumerating rows, the
-// transpose of what the projections give.  Those feature-major tiles, the
-// key-major probability and dS tiles (computed query-major) and the tiles
-// staged below are all transposed on the matrix cores (transpose_mfma: an exact
-// product with a 0/1 permutation operand).
+// transpose of what the projections give.  The key-major probability and dS tiles
+// (computed query-major) are transposed on the matrix cores (transpose_mfma: an exact
+// product with a 0/1 permutation operand).  The feature-major q, k, v, dO tiles go
+// through LDS instead: the row-major tile is written as it is and read back with
+// gfx950's transposing LDS read (ds_read_b64_tr_b16), which costs no matrix-core work.
+// Each head's products go into fresh accumulators of which only that head's features
+// are kept, so no operand is masked per head.
 //
 // Gradient phase (all waves).  x, g, O, dQ, dK, dV of each block are staged
-// in LDS as [feature][row] BF16 with the rows of each 16-row group in the
-// order of the MFMA result layout (two middle quads swapped), so that one
-// 16-byte read is a row-contraction operand.  After a workgroup barrier, wave
-// w adds the tile's 4 x 32 rows into its gradient rows.  Each workgroup writes its
-// four gradients once per launch to its partial slot [4 D^2] (Wq, Wk, Wv as
+// in LDS row-major (one 16-byte write per operand and lane, see stage_r), and read
+// back as row-contraction operands with the transposing read.  After a workgroup
+// barrier, wave w adds the tile's 4 x 32 rows into its gradient rows.  Each workgroup
+// writes its four gradients once per launch to its partial slot [4 D^2] (Wq, Wk, Wv as
 // (in, attention feature), W_O as (attention feature, out)); the slots are
 // summed in FP64 afterwards.
+//
+// The kernel for 32 < n <= 64 further down keeps the [feature][row] staging formed by
+// matrix-core transposes (stage_ops).
 #include "common.h"
 #include "net.h"
 #include "netapi.h"
@@ -69,6 +74,40 @@ __device__ __forceinline__ void stage_ops(__bf16* m, int f0, const bf16x8& o0, c
   const f32x16 t = transpose_mfma(o0, o1, eye);  // lane -> feature f0 + lr, values -> rows
 #pragma unroll
   for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(m + soff(f0 + lr, 2 * s + h)) = cvt8(t, s);
+}
+
+// Row-major staged matrix of 32 rows x 64 features (BF16) for gfx950's transposing LDS read.
+// A row is 128 bytes, 8 units of 16 bytes; unit u = 4 fb + 2 s + hh holds the two 4-feature
+// chunks 32 fb + 16 s + 4 hh + (0..3) and 32 fb + 16 s + 8 + 4 hh + (0..3): exactly the BF16
+// operand s of lane half hh of the row-major tile of feature block fb, so a lane stages an
+// operand with one 16-byte write.  Units are permuted within each 64-byte half of a row by
+// an XOR with bits 1 and 2 of the row, which keeps the 8 rows of one 16-byte write phase and
+// the 4 rows of one transposing-read phase on distinct banks.
+__device__ __forceinline__ int rsw(int u, int row) {
+  return (u & 4) | ((u & 3) ^ ((((row >> 1) & 1) << 1) | ((row >> 2) & 1)));
+}
+__device__ __forceinline__ void stage_r(__bf16* m, int fb, const bf16x8& o0, const bf16x8& o1, int lr, int h) {
+  *reinterpret_cast<bf16x8*>(m + lr * 64 + rsw(4 * fb + h, lr) * 8) = o0;
+  *reinterpret_cast<bf16x8*>(m + lr * 64 + rsw(4 * fb + 2 + h, lr) * 8) = o1;
+}
+// ds_read_b64_tr_b16: within each group of 16 lanes, lane 4t + u supplies the address of 4
+// consecutive BF16 values and lane 4u + c receives, as its value t, value c of lane 4t + u.
+__device__ __forceinline__ s16x4 tr16(const __bf16* p) {
+  return __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4*)(p));
+}
+// Element offset that lane (16 g + 4 t + u) of a transposing read addresses in a staged matrix:
+// row `row`, the 4-feature chunk 32 fb + 16 (g & 1) + 4 u; with fb = 0 (add 32 fb).
+__device__ __forceinline__ int tr_off(int row, int lane) {
+  const int g = lane >> 4, u = lane & 3;
+  return row * 64 + rsw(2 * (g & 1) + (u & 1), row) * 8 + 4 * (u >> 1);
+}
+// Feature-major operand of feature block fb read from a staged matrix: lane l gets feature
+// 32 fb + l % 32 at 8 rows, value 4 rd + t from row rows(rd, t).  off[rd] = tr_off(row of
+// this lane's t = (l & 15) >> 2, l).
+__device__ __forceinline__ bf16x8 tr_op(const __bf16* m, int fb, const int (&off)[2]) {
+  typedef short s16x8 __attribute__((ext_vector_type(8)));
+  const s16x4 a = tr16(m + off[0] + 32 * fb), b = tr16(m + off[1] + 32 * fb);
+  return __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
 // -l (a softmax normaliser negated) as three BF16 terms with hi + mid + lo = -l exactly
@@ -129,6 +168,16 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     okbits |= (other == lr / n && other < cpb) ? (1u << r) : 0u;
   }
 
+  // this lane's transposing-read offsets: rows tile_idx(8 s + 4 rd + t, l / 32), t = (l & 15) >> 2 (the
+  // key order of the score tiles, and the row order of the gradient products' K steps); rows 8 and
+  // 16 further leave the unit permutation unchanged, so the four offsets differ by constants
+  const int toff0 = tr_off(4 * h + ((lane & 15) >> 2), lane);
+  int toff[ST][2];
+#pragma unroll
+  for (int s = 0; s < ST; ++s)
+#pragma unroll
+    for (int rd = 0; rd < 2; ++rd) toff[s][rd] = toff0 + (16 * s + 8 * rd) * 64;
+
   f32x16 dW[NB];  // rows [32 hb, 32 hb + 32) of weight gradient bw
 #pragma unroll
   for (int j = 0; j < NB; ++j) dW[j] = f32x16{};
@@ -140,26 +189,32 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
   float4 gn[NB][4];
   float ln[HPB];  // the forward's log2 softmax normalisers of this lane's query row, heads of head block hb
   auto fetch = [&](int64_t tl) {
+    // the block's saved normalisers, x and g through buffer resources at the block (scalar
+    // bases and one lane offset each, no 64-bit addresses per lane); past the last block the
+    // resources are empty and the loads return zeros
     const int64_t g = 4 * tl + bw;
-    {
-      const float* ls = a.lse + (((tl < ntile && g < nblk) ? g : 0) * 32 + lr) * (NB * HPB) + hb * HPB;
-#pragma unroll
-      for (int j = 0; j < HPB; ++j) ln[j] = ls[j];
+    const bool ok = tl < ntile && g < nblk;
+    const int64_t gg = ok ? g : 0;
+    const auto lres = rsrc(a.lse + gg * 32 * (NB * HPB), ok ? 32 * NB * HPB * 4 : 0);
+    const auto xres = rsrc(reinterpret_cast<const __bf16*>(a.save_x) + gg * NB * 64 * 16, ok ? NB * 64 * 16 * 2 : 0);
+    const auto gres = rsrc(a.g_in + gg * NB * 64 * 16, ok ? NB * 64 * 16 * 4 : 0);
+    if constexpr (HPB == 4) {
+      // row lr's normalisers at lr * 32 bytes: the x offset lane * 32 with the lane half masked
+      // off, formed here (not hoisted out of the tile loop, where it would take a register)
+      int loff;
+      asm volatile("v_and_b32 %0, 0x3ff, %1" : "=v"(loff) : "v"(lane * 32));
+      const float4 v = rld4(lres, loff, hb * HPB * 4);
+      ln[0] = v.x; ln[1] = v.y; ln[2] = v.z; ln[3] = v.w;
+    } else {
+      const float2 v = rld2(lres, lr * (NB * HPB * 4) + hb * HPB * 4);
+      ln[0] = v.x; ln[1] = v.y;
     }
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) {
-      if (tl < ntile && g < nblk) {
-        const __bf16* xs = reinterpret_cast<const __bf16*>(a.save_x) + ((g * NB + ib) * 64 + lane) * 16;
-        xn[ib][0] = ld8(xs);
-        xn[ib][1] = ld8(xs + 8);
-        const float4* gs = reinterpret_cast<const float4*>(a.g_in + ((g * NB + ib) * 64 + lane) * 16);
+      xn[ib][0] = rld8(xres, lane * 32, ib * 64 * 16 * 2);
+      xn[ib][1] = rld8(xres, lane * 32, ib * 64 * 16 * 2 + 16);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) gn[ib][q] = gs[q];
-      } else {
-        xn[ib][0] = xn[ib][1] = bf16x8{};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) gn[ib][q] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+      for (int q = 0; q < 4; ++q) gn[ib][q] = rld4(gres, lane * 64, ib * 64 * 64 + 16 * q);
     }
   };
   fetch(blockIdx.x);
@@ -186,16 +241,16 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     // the wave of head block 0 stages x, the other g
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) {
-      if (hb == 0) stage_ops(S + SX * MAT, 32 * ib, xo[ib][0], xo[ib][1], eye, lr, h);
-      else stage_ops(S + SG * MAT, 32 * ib, go[ib][0], go[ib][1], eye, lr, h);
+      if (hb == 0) stage_r(S + SX * MAT, ib, xo[ib][0], xo[ib][1], lr, h);
+      else stage_r(S + SG * MAT, ib, go[ib][0], go[ib][1], lr, h);
     }
 
     // projections of the 32 attention features of head block hb, row-major (*R: lane -> row,
     // values -> features), packed to BF16 operands right away to keep the register peak low:
     // per-head score operands (q scaled by log2(e)/sqrt(dh), dO by 1/sqrt(dh)).  The
-    // feature-major tiles (*F: lane -> feature, values -> rows; masked per head below) are
-    // exact MFMA transposes of those BF16 operands, half the MFMAs of projecting again; dK
-    // and dV, formed from the scaled q and dO, are rescaled after the head loop.
+    // feature-major tiles (*F: lane -> feature, values -> rows in the key order of the score
+    // tiles) are read back transposed from LDS; dK and dV, formed from the scaled q and dO,
+    // are rescaled in the head loop.
     using sop = PBF16::SOp<DH>;
     sop QRp[HPB], KRp[HPB], VRp[HPB], ORp[HPB];
     bf16x8 QFb[ST], KFb[ST], VFb[ST], OFb[ST];
@@ -226,10 +281,12 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         QRp[j] = PBF16::pack_head<DH>(QR, j);
         KRp[j] = PBF16::pack_head<DH>(KR, j);
       }
-      const f32x16 QF = transpose_mfma(rop(QRp, 0), rop(QRp, 1), eye);
-      const f32x16 KF = transpose_mfma(rop(KRp, 0), rop(KRp, 1), eye);
+      // feature-major tiles through LDS: this wave's feature half of the dQ and dK staging
+      // slots is free until it stages dQ and dK there after the head loop
+      stage_r(S + SQ * MAT, hb, rop(QRp, 0), rop(QRp, 1), lr, h);
+      stage_r(S + SK * MAT, hb, rop(KRp, 0), rop(KRp, 1), lr, h);
 #pragma unroll
-      for (int s = 0; s < ST; ++s) { QFb[s] = cvt8(QF, s); KFb[s] = cvt8(KF, s); }
+      for (int s = 0; s < ST; ++s) { QFb[s] = tr_op(S + SQ * MAT, hb, toff[s]); KFb[s] = tr_op(S + SK * MAT, hb, toff[s]); }
     }
     {
       f32x16 VR = {}, OR = {};  // V and dO = g W_O^T
@@ -250,18 +307,27 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         VRp[j] = PBF16::pack_head<DH>(VR, j);
         ORp[j] = PBF16::pack_head<DH>(OR, j);
       }
-      const f32x16 VF = transpose_mfma(rop(VRp, 0), rop(VRp, 1), eye);
-      const f32x16 OF = transpose_mfma(rop(ORp, 0), rop(ORp, 1), eye);
+      stage_r(S + SV * MAT, hb, rop(VRp, 0), rop(VRp, 1), lr, h);
+      stage_r(S + SO * MAT, hb, rop(ORp, 0), rop(ORp, 1), lr, h);
 #pragma unroll
-      for (int s = 0; s < ST; ++s) { VFb[s] = cvt8(VF, s); OFb[s] = cvt8(OF, s); }
+      for (int s = 0; s < ST; ++s) { VFb[s] = tr_op(S + SV * MAT, hb, toff[s]); OFb[s] = tr_op(S + SO * MAT, hb, toff[s]); }
     }
     float lse[HPB];
 #pragma unroll
     for (int j = 0; j < HPB; ++j) lse[j] = ln[j];
-    f32x16 dQR = {}, dKR = {}, dVR = {}, AOF = {};  // dQ, dK, dV (R) and the attention output O (F)
+    // dQ, dK, dV and the attention output O, all row-major (lane -> row, values -> features).
+    // Each head's products go into fresh accumulators with unmasked feature-major operands:
+    // of such a product only values [VPH j, VPH (j + 1)) of each lane (the features of head j,
+    // see tile_idx) are head j's result, and they are kept; the other values, formed from head
+    // j's P or dS against other heads' features, are dropped.  No operand is masked per head.
+    // The kept values are scaled where needed (dK and dV were formed from q scaled by sc and dO
+    // scaled by 1/sqrt(dh)) and packed to BF16 operand words right away: value pair (2w, 2w + 1)
+    // is word w % 4 of operand w / 4.
+    constexpr int VPH = DH / 2;
+    const float isc = 1.0f / sc, sdh = 1.0f / isd;
+    u32x4 ow[ST], qw[ST], kw[ST], vw[ST];
 #pragma unroll
     for (int j = 0; j < HPB; ++j) {
-      const bool mine = (lr / DH) == j;
       // query-major tiles: lane -> query lr, values -> keys tile_idx(r, h)
       f32x16 sq;
       if constexpr (DH == 8) {
@@ -305,34 +371,53 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         Pk[s] = cvt8(pk, s);
         Sk[s] = cvt8(sk2, s);
       }
+      // two products at a time (four fresh accumulators at once would not fit in the registers)
+      {
+        f32x16 to = {}, tq = {};
 #pragma unroll
-      for (int s = 0; s < ST; ++s) {
-        const bf16x8 z = {};
-        AOF = mfma16(Pq[s], mine ? VFb[s] : z, AOF);  // O[q][f]  = sum_k P[q][k] V[k][f]
-        dQR = mfma16(mine ? KFb[s] : z, Sq[s], dQR);  // dQ[q][f] = sum_k dS[q][k] K[k][f]
-        dKR = mfma16(mine ? QFb[s] : z, Sk[s], dKR);  // dK[k][f] = sum_q dS[q][k] Q[q][f]
-        dVR = mfma16(mine ? OFb[s] : z, Pk[s], dVR);  // dV[k][f] = sum_q P[q][k] dO[q][f]
+        for (int s = 0; s < ST; ++s) {
+          to = mfma16(VFb[s], Pq[s], to);  // O[q][f]  = sum_k P[q][k] V[k][f]
+          tq = mfma16(KFb[s], Sq[s], tq);  // dQ[q][f] = sum_k dS[q][k] K[k][f]
+        }
+#pragma unroll
+        for (int w = VPH * j / 2; w < VPH * (j + 1) / 2; ++w) {
+          ow[w / 4][w % 4] = pk2(to[2 * w], to[2 * w + 1]);
+          qw[w / 4][w % 4] = pk2(tq[2 * w], tq[2 * w + 1]);
+        }
       }
-    }
-    // stage dQ, dK, dV (R layout -> [feature][row]) and O (F layout: two 16-byte writes per lane)
-    // dK and dV were formed from q scaled by sc and dO scaled by 1/sqrt(dh)
-    {
-      const float isc = 1.0f / sc, sdh = 1.0f / isd;
+      {
+        f32x16 tk = {}, tv = {};
 #pragma unroll
-      for (int r = 0; r < 16; ++r) { dKR[r] *= isc; dVR[r] *= sdh; }
+        for (int s = 0; s < ST; ++s) {
+          tk = mfma16(QFb[s], Sk[s], tk);  // dK[k][f] = sum_q dS[q][k] Q[q][f]
+          tv = mfma16(OFb[s], Pk[s], tv);  // dV[k][f] = sum_q P[q][k] dO[q][f]
+        }
+#pragma unroll
+        for (int w = VPH * j / 2; w < VPH * (j + 1) / 2; ++w) {
+          kw[w / 4][w % 4] = pk2(tk[2 * w] * isc, tk[2 * w + 1] * isc);
+          vw[w / 4][w % 4] = pk2(tv[2 * w] * sdh, tv[2 * w + 1] * sdh);
+        }
+      }
+      // heads are independent now: keep the scheduler from interleaving them, which would
+      // hold several heads' score tiles and accumulators in registers at once
+      __builtin_amdgcn_sched_barrier(0);
     }
+    // stage dQ, dK, dV and O (R layout -> [feature][row])
     bf16x8 dq[ST], dk[ST], dv[ST];
 #pragma unroll
-    for (int s = 0; s < ST; ++s) { dq[s] = cvt8(dQR, s); dk[s] = cvt8(dKR, s); dv[s] = cvt8(dVR, s); }
-    stage_ops(S + SQ * MAT, 32 * hb, dq[0], dq[1], eye, lr, h);
-    stage_ops(S + SK * MAT, 32 * hb, dk[0], dk[1], eye, lr, h);
-    stage_ops(S + SV * MAT, 32 * hb, dv[0], dv[1], eye, lr, h);
-#pragma unroll
-    for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + soff(32 * hb + lr, 2 * s + h)) = cvt8(AOF, s);
-    // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T.  The wave of head block 0 adds its terms to g and
-    // leaves the sum in LDS; after the barrier the wave of head block 1 adds its terms and
-    // writes dx (lane l of both waves holds the same rows and features).  The products start
-    // from zero and the loaded part is added last, so that its load overlaps them.
+    for (int s = 0; s < ST; ++s) {
+      dq[s] = __builtin_bit_cast(bf16x8, qw[s]);
+      dk[s] = __builtin_bit_cast(bf16x8, kw[s]);
+      dv[s] = __builtin_bit_cast(bf16x8, vw[s]);
+    }
+    stage_r(S + SQ * MAT, hb, dq[0], dq[1], lr, h);
+    stage_r(S + SK * MAT, hb, dk[0], dk[1], lr, h);
+    stage_r(S + SV * MAT, hb, dv[0], dv[1], lr, h);
+    stage_r(S + SO * MAT, hb, __builtin_bit_cast(bf16x8, ow[0]), __builtin_bit_cast(bf16x8, ow[1]), lr, h);
+    // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T.  The wave of head block 0 leaves its terms in LDS;
+    // after the barrier the wave of head block 1 adds g and its own terms and writes dx (lane l
+    // of both waves holds the same rows and features).  g is loaded by head block 1 before the
+    // barrier, where that wave waits for the other one anyway: the load is off the critical path.
     auto dx_terms = [&](int ob) {
       f32x16 acc = {};
       const int voff = (hb * ST * 64 + lane) * 16;  // fragment ((ob NB + hb) ST + s) of each matrix
@@ -346,31 +431,40 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       return acc;
     };
     float4* X = xch + bw * NB * 4 * 64;
+    // the block's g and dx through buffer resources at the block (a wave-uniform base and one
+    // lane offset, instead of 64-bit addresses per lane kept live across the tile loop); empty
+    // past the last block
+    constexpr uint32_t BLK_BYTES = NB * 64 * 16 * sizeof(float);
+    const auto gres = rsrc(a.g_in + (valid ? gb : 0) * NB * 64 * 16, valid ? BLK_BYTES : 0);
+    const auto dres = rsrc(a.g_out + (valid ? gb : 0) * NB * 64 * 16, valid ? BLK_BYTES : 0);
+    float4 sv[NB][4];
     if (hb == 0 && valid) {
-      float4 sv[NB][4];
-#pragma unroll
-      for (int ob = 0; ob < NB; ++ob)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) sv[ob][q] = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + ob) * 64 + lane) * 16)[q];
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob) {
         const f32x16 acc = dx_terms(ob);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          X[(ob * 4 + q) * 64 + lane] = make_float4(sv[ob][q].x + acc[4 * q], sv[ob][q].y + acc[4 * q + 1],
-                                                     sv[ob][q].z + acc[4 * q + 2], sv[ob][q].w + acc[4 * q + 3]);
+          X[(ob * 4 + q) * 64 + lane] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
       }
+    } else if (hb == 1) {
+#pragma unroll
+      for (int ob = 0; ob < NB; ++ob)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sv[ob][q] = rld4(gres, lane * 64, ob * 64 * 64 + 16 * q);
     }
     barrier_lds();  // staging and head block 0's part of dx in LDS
     if (hb == 1 && valid) {
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob) {
         const f32x16 acc = dx_terms(ob);
-        float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + ob) * 64 + lane) * 16);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const float4 v = X[(ob * 4 + q) * 64 + lane];
-          dst[q] = make_float4(v.x + acc[4 * q], v.y + acc[4 * q + 1], v.z + acc[4 * q + 2], v.w + acc[4 * q + 3]);
+          const float4 g = sv[ob][q];
+          rst4(dres, lane * 64,
+               make_float4((g.x + v.x) + acc[4 * q], (g.y + v.y) + acc[4 * q + 1], (g.z + v.z) + acc[4 * q + 2],
+                           (g.w + v.w) + acc[4 * q + 3]),
+               ob * 64 * 64 + 16 * q);
         }
       }
     }
@@ -387,10 +481,10 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         const __bf16* B = stg + (b * NSTAGE + bm) * MAT;
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
-          const bf16x8 av = ld8(A + soff(32 * hb + lr, 2 * s + h));
+          const bf16x8 av = tr_op(A, hb, toff[s]);
           bf16x8 bv[NB];
 #pragma unroll
-          for (int j = 0; j < NB; ++j) bv[j] = ld8(B + soff(32 * j + lr, 2 * s + h));
+          for (int j = 0; j < NB; ++j) bv[j] = tr_op(B, j, toff[s]);
 #pragma unroll
           for (int j = 0; j < NB; ++j) dW[j] = mfma16(av, bv[j], dW[j]);
         }

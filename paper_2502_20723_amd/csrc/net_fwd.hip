@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
           }
       }
       // score scale folded into q; per-head score operands of q and k packed once per head
-      // block; V as operands (lane -> feature), masked to one head below
+      // block; V as operands (lane -> feature)
       using sop = typename P::template SOp<DH>;
       sop qp[NBR][HPB], kp[NBR][HPB];
 #pragma unroll
@@ -272,14 +272,15 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
       for (int kb = 0; kb < NBR; ++kb)
 #pragma unroll
         for (int s = 0; s < ST; ++s) vop[kb][s] = P::op(v[kb], s);
+      // o = P V per head, row-major (lane -> row, values -> features).  Each head's product goes
+      // into a fresh accumulator with the unmasked V operand (lane -> feature): only values
+      // [VPH j, VPH (j + 1)) of each lane (the features of head j, see tile_idx) are head j's
+      // output and are kept, normalised; the other values are dropped.
+      constexpr int VPH = DH / 2;
       f32x16 o[NBR];
-      float invl[NBR][HPB];
       float lsev[NBR][HPB];  // log2 softmax normalisers of this lane's row in each row block
 #pragma unroll
-      for (int rb = 0; rb < NBR; ++rb) o[rb] = f32x16{};
-#pragma unroll
       for (int j = 0; j < HPB; ++j) {
-        const bool mine = (lr / DH) == j;
 #pragma unroll
         for (int qb = 0; qb < NBR; ++qb) {
           f32x16 st[NBR];
@@ -314,13 +315,16 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
           const float l = xor32_sum(part[0]);
           // l >= 1 when the row has a key (its maximum contributes exp2(0)): the hardware
           // reciprocal (1 ulp) replaces the division sequence
-          invl[qb][j] = l > 0.f ? __builtin_amdgcn_rcpf(l) : 0.f;
+          const float invl = l > 0.f ? __builtin_amdgcn_rcpf(l) : 0.f;
           // for the backward: P = exp2(s - lse) (+inf for a row with no key, so that P = 0)
           lsev[qb][j] = l > 0.f ? mm + __builtin_amdgcn_logf(l) : INFINITY;
+          f32x16 to = {};
 #pragma unroll
           for (int kb = 0; kb < NBR; ++kb)
 #pragma unroll
-            for (int s = 0; s < ST; ++s) o[qb] = P::mma(mine ? vop[kb][s] : op_t{}, P::op(st[kb], s), o[qb]);
+            for (int s = 0; s < ST; ++s) to = P::mma(vop[kb][s], P::op(st[kb], s), to);
+#pragma unroll
+          for (int r = VPH * j; r < VPH * (j + 1); ++r) o[qb][r] = to[r] * invl;
         }
       }
       if constexpr (P::KPL == 8) {
@@ -336,11 +340,9 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
           else rst2(rl, off, make_float2(lsev[qb][0], lsev[qb][1]));
         }
       }
-      // normalise per head, then W_O into the residual
+      // W_O into the residual
 #pragma unroll
       for (int qb = 0; qb < NBR; ++qb) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) o[qb][r] *= invl[qb][DH == 8 ? r / 4 : r / 8];  // value r holds a feature of head r*4/DH
 #pragma unroll
         for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
