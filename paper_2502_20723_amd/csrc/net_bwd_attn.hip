@@ -19,13 +19,12 @@
 //
 // Block phase (one wave per head block).  Every contraction over keys or queries needs its
 // operands with lanes enumerating features and values enumerating rows, the
-// transpose of what the projections give.  The key-major probability and dS tiles
-// (computed query-major) are transposed on the matrix cores (transpose_mfma: an exact
-// product with a 0/1 permutation operand).  The feature-major q, k, v, dO tiles go
-// through LDS instead: the row-major tile is written as it is and read back with
-// gfx950's transposing LDS read (ds_read_b64_tr_b16), which costs no matrix-core work.
-// Each head's products go into fresh accumulators of which only that head's features
-// are kept, so no operand is masked per head.
+// transpose of what the projections give, and the contractions over queries need the
+// probability and dS tiles key-major, the transpose of how they are computed.  All of these
+// go through LDS: the tile is written as it is and read back with gfx950's transposing LDS
+// read (ds_read_b64_tr_b16), which costs no matrix-core work.  Each head's products go
+// into fresh accumulators of which only that head's features are kept, so no operand is
+// masked per head.
 //
 // Gradient phase (all waves).  x, g, O, dQ, dK, dV of each block are staged
 // in LDS row-major (one 16-byte write per operand and lane, see stage_r), and read
@@ -153,12 +152,6 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
   const int64_t nblk = 2 * ((E + cpb - 1) / cpb);
   const int64_t ntile = (nblk + 3) / 4;
   const float sc = a.score_scale, isd = a.inv_sqrt_dh;
-  // permutation operands of transpose_mfma: eye[s][t] = [tile_idx(8 s + t, h) == lr]
-  bf16x8 eye[2];
-#pragma unroll
-  for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-    for (int t2 = 0; t2 < 8; ++t2) eye[s2][t2] = (__bf16)(tile_idx(8 * s2 + t2, h) == lr ? 1.0f : 0.0f);
   // valid (query, key) pairs of this lane's row lr against rows tile_idx(r, h): same configuration
   // slot, slot < cpb (symmetric, so the same bits serve query-major and key-major tiles)
   uint32_t okbits = 0;
@@ -363,14 +356,12 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       bf16x8 Pq[ST], Sq[ST];
 #pragma unroll
       for (int s = 0; s < ST; ++s) { Pq[s] = cvt8(sq, s); Sq[s] = cvt8(dpq, s); }
-      // key-major P and dS (lane -> key, values -> queries): exact MFMA transposes
-      const f32x16 pk = transpose_mfma(Pq[0], Pq[1], eye), sk2 = transpose_mfma(Sq[0], Sq[1], eye);
-      bf16x8 Pk[ST], Sk[ST];
-#pragma unroll
-      for (int s = 0; s < ST; ++s) {
-        Pk[s] = cvt8(pk, s);
-        Sk[s] = cvt8(sk2, s);
-      }
+      // key-major P and dS (lane -> key, values -> queries) through LDS: written query-major into
+      // this wave's half of the dQ and dK staging slots (free until the staging after the head loop;
+      // the previous head's reads of them are ordered before these writes), read back transposed
+      // after the query-major products below are issued
+      stage_r(S + SQ * MAT, hb, Pq[0], Pq[1], lr, h);
+      stage_r(S + SK * MAT, hb, Sq[0], Sq[1], lr, h);
       // two products at a time (four fresh accumulators at once would not fit in the registers)
       {
         f32x16 to = {}, tq = {};
@@ -386,6 +377,9 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         }
       }
       {
+        bf16x8 Pk[ST], Sk[ST];
+#pragma unroll
+        for (int s = 0; s < ST; ++s) { Pk[s] = tr_op(S + SQ * MAT, hb, toff[s]); Sk[s] = tr_op(S + SK * MAT, hb, toff[s]); }
         f32x16 tk = {}, tv = {};
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
@@ -400,7 +394,6 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       }
       // heads are independent now: keep the scheduler from interleaving them, which would
       // hold several heads' score tiles and accumulators in registers at once
-      __builtin_amdgcn_sched_barrier(0);
     }
     // stage dQ, dK, dV and O (R layout -> [feature][row])
     bf16x8 dq[ST], dk[ST], dv[ST];
