@@ -58,6 +58,20 @@ __device__ __forceinline__ f32x16 transpose_mfma(const bf16x8& x0, const bf16x8&
   return mfma16(x1, eye[1], mfma16(x0, eye[0], f32x16{}));
 }
 
+// gfx950's transposing LDS read (ds_read_b64_tr_b16): within each group of 16 lanes, lane
+// 4t + u supplies the address of 4 consecutive BF16 values and lane 4u + c receives, as its
+// value t, value c of lane 4t + u.  On a tile stored as rows of 4-column chunks (the perm16
+// order keeps each chunk contiguous), two such reads give lane l column l % 32 at 8 rows:
+// the row-contraction operand of the tile, with no transpose on the matrix cores.  p points
+// at (first row, first column) of the 32 x 32 part read; off is the lane's offset (toff).
+__device__ __forceinline__ bf16x8 tr_op(const __bf16* p, int off) {
+  typedef short s16x8 __attribute__((ext_vector_type(8)));
+  typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+  const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + off));
+  const s16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + off + 8 * XS));
+  return __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 }  // namespace
 
 // SEEDS: the last layer, whose incoming gradient is formed from the per-configuration seeds
@@ -328,16 +342,17 @@ __global__ void __launch_bounds__(256) k_bwd_mlp_bf16(BwdArgs a) {
 // wave q sums hidden [128, 256) and leaves its part in LDS; after a barrier wave q + 4,
 // which staged g of the same tile, adds hidden [0, 128), that part and the residual, and
 // writes dx.  Every cross-wave use of LDS is ordered by one of the three barriers of a tile.
+// Unlike the 4-wave kernel, no tile is transposed on the matrix cores: the contractions over
+// rows read x and g, and dx reads du, with gfx950's transposing LDS read (tr_op), from
+// x and g staged row-major and du staged as (hidden x row), the orientation it is formed in.
 template <bool SEEDS>
 __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
   constexpr int M = 256, D = 64, NB = 2, DUS = M + 8;
   extern __shared__ __align__(16) char smem[];
   __bf16* XA = reinterpret_cast<__bf16*>(smem);  // [RT][XS]   x, row-major (features in perm16 order)
-  __bf16* XT = XA + RT * XS;                      // [D][XS]    x^T, rows in perm16 order
-  __bf16* GA = XT + D * XS;                       // [RT][XS]   g, row-major
-  __bf16* GT = GA + RT * XS;                      // [D][XS]    g^T
-  __bf16* DU = GT + D * XS;                       // [RT][DUS]  du, row-major, hidden units in perm16 order
-  __bf16* W1s = DU + RT * DUS;                    // [D][DUS]   W1 (operand of dx = du W1^T), same order
+  __bf16* GA = XA + RT * XS;                      // [RT][XS]   g, row-major
+  __bf16* DT = GA + RT * XS;                      // [M][XS]    du, (hidden x row), rows in perm16 order
+  __bf16* W1s = DT + M * XS;                      // [D][DUS]   W1 (operand of dx = du W1^T), hidden in perm16 order
   float* db2s = reinterpret_cast<float*>(W1s + D * DUS);     // [2 blocks of the tile][D]
   float4* GF = reinterpret_cast<float4*>(db2s + 2 * D);      // [4 roles][4][64]: g in FP32
   float4* XD = GF + 4 * 4 * 64;                              // [4 tiles][4][64]: dx over hidden [128, 256)
@@ -366,11 +381,10 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
   for (int i = t; i < D * M; i += 512) W1s[(i / M) * DUS + perm16(i % M)] = (__bf16)a.w1[i];
   if constexpr (SEEDS)
     for (int i = t; i < D; i += 512) hws[i] = i < a.d_real ? make_float2(a.head_w[2 * i], a.head_w[2 * i + 1]) : make_float2(0.f, 0.f);
-  bf16x8 eye[2];  // permutation operands of transpose_mfma
-#pragma unroll
-  for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-    for (int t2 = 0; t2 < 8; ++t2) eye[s2][t2] = (__bf16)(tile_idx(8 * s2 + t2, h) == lr ? 1.0f : 0.0f);
+  // this lane's transposing-read offset (see tr_op) at row 4 h + t of a 64-wide perm16 tile:
+  // rows 32 rb + 16 s + 8 rd + 4 h + t (= 32 rb + tile_idx(8 s + 4 rd + t, h)) and 4 columns
+  // 32 fb + 16 (g & 1) + 4 u add constants (with g = lane / 16, t = lane % 16 / 4, u = lane % 4)
+  const int toff = (4 * h + ((lane & 15) >> 2)) * XS + 16 * ((lane >> 4) & 1) + 8 * (lane & 1) + 4 * ((lane >> 1) & 1);
   __syncthreads();  // W1s and the head weights initialised before any use
   const float bias = a.b1[hid];
 
@@ -421,9 +435,6 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
     if (!gw) {
 #pragma unroll
       for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(XA + srow * XS + 32 * sob + 16 * s + 8 * h) = xn[s];
-      const f32x16 xt = transpose_mfma(xn[0], xn[1], eye);
-#pragma unroll
-      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(XT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = cvt8(xt, s);
     } else {
       float g[16];
       if constexpr (SEEDS) {
@@ -449,9 +460,6 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
       for (int k = 0; k < 4; ++k) GF[(q * 4 + k) * 64 + lane] = make_float4(g[4 * k], g[4 * k + 1], g[4 * k + 2], g[4 * k + 3]);
 #pragma unroll
       for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(GA + srow * XS + 32 * sob + 16 * s + 8 * h) = go[s];
-      const f32x16 gt = transpose_mfma(go[0], go[1], eye);
-#pragma unroll
-      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(GT + (32 * sob + lr) * XS + 32 * sb + 16 * s + 8 * h) = cvt8(gt, s);
     }
     barrier_lds();
     fetch(tile + gridDim.x);
@@ -477,23 +485,19 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
         dh[r] = d;                   // du
         db1 += d;
       }
-      bf16x8 duo[2];
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
         const int pos = 32 * rb + 16 * s + 8 * h;
-        duo[s] = cvt8(dh, s);
-        const bf16x8 ho = cvt8(u, s);
+        const bf16x8 duo = cvt8(dh, s), ho = cvt8(u, s);
+        // du as (hidden x row): one 16-byte write per lane, the layout x and g are staged in
+        *reinterpret_cast<bf16x8*>(DT + hid * XS + pos) = duo;
+        const int ro = (32 * rb + 16 * s) * XS;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-          dW1[i] = mfma16(ld8(XT + (32 * i + lr) * XS + pos), duo[s], dW1[i]);  // (in x hidden)
-          dW2[i] = mfma16(ho, ld8(GT + (32 * i + lr) * XS + pos), dW2[i]);      // (hidden x out)
+          dW1[i] = mfma16(tr_op(XA + ro + 32 * i, toff), duo, dW1[i]);  // (in x hidden)
+          dW2[i] = mfma16(ho, tr_op(GA + ro + 32 * i, toff), dW2[i]);   // (hidden x out)
         }
       }
-      // du transposed (lane -> row, values -> hidden units in perm16 order), 16-byte writes
-      const f32x16 dut = transpose_mfma(duo[0], duo[1], eye);
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-        *reinterpret_cast<bf16x8*>(DU + (32 * rb + lr) * DUS + 32 * w + 16 * s + 8 * h) = cvt8(dut, s);
     }
     barrier_lds();
 
@@ -503,7 +507,7 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
 #pragma unroll
     for (int s = 0; s < (M / 16) / 2; ++s)  // A[m = in][k = hidden] = W1, B[k = hidden][n = row] = du
       acc = mfma16(ld8(W1s + (32 * sob + lr) * DUS + 16 * (k0 + s) + 8 * h),
-                   ld8(DU + (32 * sb + lr) * DUS + 16 * (k0 + s) + 8 * h), acc);
+                   tr_op(DT + 16 * (k0 + s) * XS + 32 * sb, toff), acc);
     if (!gw) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -550,7 +554,7 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
 }
 
 size_t bwd_mlp8_bf16_lds() {
-  return (size_t)(2 * RT * XS + 2 * 64 * XS + (RT + 64) * (256 + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float) +
+  return (size_t)(2 * RT * XS + 256 * XS + 64 * (256 + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float) +
          2 * 4 * 4 * 64 * sizeof(float4) + 64 * sizeof(float2);
 }
 
