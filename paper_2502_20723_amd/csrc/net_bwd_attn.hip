@@ -34,8 +34,7 @@
 // (in, attention feature), W_O as (attention feature, out)); the slots are
 // summed in FP64 afterwards.
 //
-// The kernel for 32 < n <= 64 further down keeps the [feature][row] staging formed by
-// matrix-core transposes (stage_ops).
+// The kernel for 32 < n <= 64 further down works the same way over two row blocks.
 #include "common.h"
 #include "net.h"
 #include "netapi.h"
@@ -44,46 +43,25 @@ namespace tdo {
 
 namespace {
 
-constexpr int FS = 32;               // row stride (bf16) of a staged [feature][row] matrix (64 bytes)
-constexpr int MAT = 64 * FS;         // one staged matrix
-// Element offset of the 16-byte chunk c (rows 8c .. 8c+7 of the position order) of feature
-// f in a staged matrix.  The chunks of a feature are permuted by an XOR of bits of f so that
-// the 8 or 16 consecutive lanes of one 16-byte LDS access phase (consecutive features, same
-// c) fall on distinct banks without padding the rows.
-__device__ __forceinline__ int soff(int f, int c) { return f * FS + 8 * (c ^ (((f >> 1) ^ (f >> 3)) & 3)); }
+constexpr int MAT = 64 * 32;  // one staged matrix: 32 rows x 64 features (BF16)
 enum { SX = 0, SG = 1, SQ = 2, SK = 3, SV = 4, SO = 5, NSTAGE = 6 };
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 __device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
-// Exact transpose of a 32x32 tile on the matrix cores.  With the tile as A operand
-// (lane -> m, values -> k in the result order of the k-steps) and the 0/1 matrix
-// B[k][n] = [index of k == n] (eye, built once), C = A B has lanes enumerating the
-// former value index and values the former lane index: the tile transposed,
-// returned in the MFMA result layout.  The BF16 inputs pass through unchanged.
-__device__ __forceinline__ f32x16 transpose_mfma(const bf16x8& x0, const bf16x8& x1, const bf16x8 (&eye)[2]) {
-  return mfma16(x1, eye[1], mfma16(x0, eye[0], f32x16{}));
-}
-// R-layout tile (lane -> row, values -> features f0 + tile_idx(r, h)), given as its two
-// BF16 operands, into a staged [feature][row position] matrix: transposed by MFMA, then
-// two 16-byte writes per lane.
-__device__ __forceinline__ void stage_ops(__bf16* m, int f0, const bf16x8& o0, const bf16x8& o1,
-                                          const bf16x8 (&eye)[2], int lr, int h) {
-  const f32x16 t = transpose_mfma(o0, o1, eye);  // lane -> feature f0 + lr, values -> rows
-#pragma unroll
-  for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(m + soff(f0 + lr, 2 * s + h)) = cvt8(t, s);
-}
-
 // Row-major staged matrix of 32 rows x 64 features (BF16) for gfx950's transposing LDS read.
 // A row is 128 bytes, 8 units of 16 bytes; unit u = 4 fb + 2 s + hh holds the two 4-feature
 // chunks 32 fb + 16 s + 4 hh + (0..3) and 32 fb + 16 s + 8 + 4 hh + (0..3): exactly the BF16
 // operand s of lane half hh of the row-major tile of feature block fb, so a lane stages an
-// operand with one 16-byte write.  Units are permuted within each 64-byte half of a row by
-// an XOR with bits 1 and 2 of the row, which keeps the 8 rows of one 16-byte write phase and
-// the 4 rows of one transposing-read phase on distinct banks.
+// operand with one 16-byte write.  Unit u of row r sits at position u ^ f(r), f(r) = (bit 1 of
+// r, bit 2 of r, bit 0 of r) as bits (2, 1, 0).  Measured on gfx950 (bank-conflict counter of
+// an LDS probe): a 16-byte write serves 8 lanes per cycle over 128 bytes, a transposing read 32
+// lanes per cycle over 64 banks of 4 bytes; f gives the 8 rows of a write phase 8 distinct
+// units and the 4 rows of a read phase (rows 4k .. 4k+3, both feature halves) 64 distinct
+// banks.
 __device__ __forceinline__ int rsw(int u, int row) {
-  return (u & 4) | ((u & 3) ^ ((((row >> 1) & 1) << 1) | ((row >> 2) & 1)));
+  return u ^ ((((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1) | (row & 1));
 }
 __device__ __forceinline__ void stage_r(__bf16* m, int fb, const bf16x8& o0, const bf16x8& o1, int lr, int h) {
   *reinterpret_cast<bf16x8*>(m + lr * 64 + rsw(4 * fb + h, lr) * 8) = o0;
@@ -95,17 +73,18 @@ __device__ __forceinline__ s16x4 tr16(const __bf16* p) {
   return __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s16x4*)(p));
 }
 // Element offset that lane (16 g + 4 t + u) of a transposing read addresses in a staged matrix:
-// row `row`, the 4-feature chunk 32 fb + 16 (g & 1) + 4 u; with fb = 0 (add 32 fb).
-__device__ __forceinline__ int tr_off(int row, int lane) {
+// row `row`, the 4-feature chunk 16 (g & 1) + 4 u of feature block fb.
+__device__ __forceinline__ int tr_off(int row, int fb, int lane) {
   const int g = lane >> 4, u = lane & 3;
-  return row * 64 + rsw(2 * (g & 1) + (u & 1), row) * 8 + 4 * (u >> 1);
+  return row * 64 + rsw(4 * fb + 2 * (g & 1) + (u & 1), row) * 8 + 4 * (u >> 1);
 }
-// Feature-major operand of feature block fb read from a staged matrix: lane l gets feature
-// 32 fb + l % 32 at 8 rows, value 4 rd + t from row rows(rd, t).  off[rd] = tr_off(row of
-// this lane's t = (l & 15) >> 2, l).
-__device__ __forceinline__ bf16x8 tr_op(const __bf16* m, int fb, const int (&off)[2]) {
+// Feature-major operand read from a staged matrix: lane l gets feature 32 fb + l % 32 at 8 rows,
+// value 4 rd + t from row 8 rd + (row of off).  off = tr_off(row of this lane's t, fb, l) plus
+// the offset of whole 16-row parts; 8 rows further keep the unit positions (f reads rows
+// modulo 8), so the second read is 512 elements on.
+__device__ __forceinline__ bf16x8 tr_op(const __bf16* m, int off) {
   typedef short s16x8 __attribute__((ext_vector_type(8)));
-  const s16x4 a = tr16(m + off[0] + 32 * fb), b = tr16(m + off[1] + 32 * fb);
+  const s16x4 a = tr16(m + off), b = tr16(m + off + 8 * 64);
   return __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
@@ -161,15 +140,11 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     okbits |= (other == lr / n && other < cpb) ? (1u << r) : 0u;
   }
 
-  // this lane's transposing-read offsets: rows tile_idx(8 s + 4 rd + t, l / 32), t = (l & 15) >> 2 (the
-  // key order of the score tiles, and the row order of the gradient products' K steps); rows 8 and
-  // 16 further leave the unit permutation unchanged, so the four offsets differ by constants
-  const int toff0 = tr_off(4 * h + ((lane & 15) >> 2), lane);
-  int toff[ST][2];
-#pragma unroll
-  for (int s = 0; s < ST; ++s)
-#pragma unroll
-    for (int rd = 0; rd < 2; ++rd) toff[s][rd] = toff0 + (16 * s + 8 * rd) * 64;
+  // this lane's transposing-read offsets per feature block: rows tile_idx(8 s + 4 rd + t, l / 32),
+  // t = (l & 15) >> 2 (the key order of the score tiles, and the row order of the gradient
+  // products' K steps), 16 s rows on for operand s
+  const int tb[2] = {tr_off(4 * h + ((lane & 15) >> 2), 0, lane), tr_off(4 * h + ((lane & 15) >> 2), 1, lane)};
+  const int thb = hb ? tb[1] : tb[0];
 
   f32x16 dW[NB];  // rows [32 hb, 32 hb + 32) of weight gradient bw
 #pragma unroll
@@ -279,7 +254,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       stage_r(S + SQ * MAT, hb, rop(QRp, 0), rop(QRp, 1), lr, h);
       stage_r(S + SK * MAT, hb, rop(KRp, 0), rop(KRp, 1), lr, h);
 #pragma unroll
-      for (int s = 0; s < ST; ++s) { QFb[s] = tr_op(S + SQ * MAT, hb, toff[s]); KFb[s] = tr_op(S + SK * MAT, hb, toff[s]); }
+      for (int s = 0; s < ST; ++s) { QFb[s] = tr_op(S + SQ * MAT, thb + 1024 * s); KFb[s] = tr_op(S + SK * MAT, thb + 1024 * s); }
     }
     {
       f32x16 VR = {}, OR = {};  // V and dO = g W_O^T
@@ -303,7 +278,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       stage_r(S + SV * MAT, hb, rop(VRp, 0), rop(VRp, 1), lr, h);
       stage_r(S + SO * MAT, hb, rop(ORp, 0), rop(ORp, 1), lr, h);
 #pragma unroll
-      for (int s = 0; s < ST; ++s) { VFb[s] = tr_op(S + SV * MAT, hb, toff[s]); OFb[s] = tr_op(S + SO * MAT, hb, toff[s]); }
+      for (int s = 0; s < ST; ++s) { VFb[s] = tr_op(S + SV * MAT, thb + 1024 * s); OFb[s] = tr_op(S + SO * MAT, thb + 1024 * s); }
     }
     float lse[HPB];
 #pragma unroll
@@ -379,7 +354,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       {
         bf16x8 Pk[ST], Sk[ST];
 #pragma unroll
-        for (int s = 0; s < ST; ++s) { Pk[s] = tr_op(S + SQ * MAT, hb, toff[s]); Sk[s] = tr_op(S + SK * MAT, hb, toff[s]); }
+        for (int s = 0; s < ST; ++s) { Pk[s] = tr_op(S + SQ * MAT, thb + 1024 * s); Sk[s] = tr_op(S + SK * MAT, thb + 1024 * s); }
         f32x16 tk = {}, tv = {};
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
@@ -474,10 +449,10 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         const __bf16* B = stg + (b * NSTAGE + bm) * MAT;
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
-          const bf16x8 av = tr_op(A, hb, toff[s]);
+          const bf16x8 av = tr_op(A, thb + 1024 * s);
           bf16x8 bv[NB];
 #pragma unroll
-          for (int j = 0; j < NB; ++j) bv[j] = tr_op(B, j, toff[s]);
+          for (int j = 0; j < NB; ++j) bv[j] = tr_op(B, tb[j] + 1024 * s);
 #pragma unroll
           for (int j = 0; j < NB; ++j) dW[j] = mfma16(av, bv[j], dW[j]);
         }
@@ -498,10 +473,12 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
 // all its registers) walks tiles of 4 blocks = 2 configuration-passes; wave w handles head
 // block w % 2 of configuration-pass w / 2 over both of its blocks: score, P and dS tiles are
 // 2 x 2 (query block x key block), P comes from the forward's normalisers, dK and dV of a
-// key block sum over both query blocks.  Staging, the dx exchange through LDS and the
-// per-wave weight gradients (wave w owns all of Wq, Wk, Wv, W_O for w = 0..3) are those of
-// the kernel above with 4 waves.  Padding rows add nothing: their keys have P = 0 and
-// their incoming gradient is 0 (it is formed from the seeds of valid rows only).
+// key block sum over both query blocks.  Staging, the transposes through the transposing
+// LDS read, the dx exchange through LDS and the per-wave weight gradients (wave w owns all
+// of Wq, Wk, Wv, W_O for w = 0..3) are those of the kernel above with 4 waves; the products
+// keep feature-major operands masked per head (fresh accumulators per head would not fit
+// next to the 2 x 2 tiles).  Padding rows add nothing: their keys have P = 0 and their
+// incoming gradient is 0 (it is formed from the seeds of valid rows only).
 template <int DH, bool MASKED>
 __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
   constexpr int D = 64, NB = 2, ST = 2, HPB = 32 / DH;
@@ -528,11 +505,9 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
   const int n = a.n;
   const int64_t ntile = E;  // 4 blocks (2 configuration-passes) per entry
   const float sc = a.score_scale, isd = a.inv_sqrt_dh;
-  bf16x8 eye[2];
-#pragma unroll
-  for (int s2 = 0; s2 < 2; ++s2)
-#pragma unroll
-    for (int t2 = 0; t2 < 8; ++t2) eye[s2][t2] = (__bf16)(tile_idx(8 * s2 + t2, h) == lr ? 1.0f : 0.0f);
+  // transposing-read offsets, as in the kernel above
+  const int tb[2] = {tr_off(4 * h + ((lane & 15) >> 2), 0, lane), tr_off(4 * h + ((lane & 15) >> 2), 1, lane)};
+  const int thb = hb ? tb[1] : tb[0];
   // valid keys of the second key block: rows 32 + tile_idx(r, h) < n (the first block is all valid)
   uint32_t ok1 = 0;
 #pragma unroll
@@ -596,12 +571,13 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
       __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
 #pragma unroll
       for (int ib = 0; ib < NB; ++ib) {
-        if (hb == 0) stage_ops(S + SX * MAT, 32 * ib, xo[rb][ib][0], xo[rb][ib][1], eye, lr, h);
-        else stage_ops(S + SG * MAT, 32 * ib, go[rb][ib][0], go[rb][ib][1], eye, lr, h);
+        if (hb == 0) stage_r(S + SX * MAT, ib, xo[rb][ib][0], xo[rb][ib][1], lr, h);
+        else stage_r(S + SG * MAT, ib, go[rb][ib][0], go[rb][ib][1], lr, h);
       }
     }
     // projections of head block hb for both blocks (see the kernel above: the feature-major
-    // tiles are MFMA transposes of the row-major BF16 operands; dK, dV rescaled below)
+    // tiles are read back transposed from this wave's half of the dQ..O staging slots; dK, dV
+    // rescaled below)
     using sop = PBF16::SOp<DH>;
     sop QRp[2][HPB], KRp[2][HPB], VRp[2][HPB], ORp[2][HPB];
     bf16x8 QFb[2][ST], KFb[2][ST], VFb[2][ST], OFb[2][ST];
@@ -633,10 +609,14 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           QRp[rb][j] = PBF16::pack_head<DH>(QR, j);
           KRp[rb][j] = PBF16::pack_head<DH>(KR, j);
         }
-        const f32x16 QF = transpose_mfma(rop(QRp[rb], 0), rop(QRp[rb], 1), eye);
-        const f32x16 KF = transpose_mfma(rop(KRp[rb], 0), rop(KRp[rb], 1), eye);
+        __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
+        stage_r(S + SQ * MAT, hb, rop(QRp[rb], 0), rop(QRp[rb], 1), lr, h);
+        stage_r(S + SK * MAT, hb, rop(KRp[rb], 0), rop(KRp[rb], 1), lr, h);
 #pragma unroll
-        for (int s = 0; s < ST; ++s) { QFb[rb][s] = cvt8(QF, s); KFb[rb][s] = cvt8(KF, s); }
+        for (int s = 0; s < ST; ++s) {
+          QFb[rb][s] = tr_op(S + SQ * MAT, thb + 1024 * s);
+          KFb[rb][s] = tr_op(S + SK * MAT, thb + 1024 * s);
+        }
       }
       {
         f32x16 VR = {}, OR = {};
@@ -657,15 +637,25 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           VRp[rb][j] = PBF16::pack_head<DH>(VR, j);
           ORp[rb][j] = PBF16::pack_head<DH>(OR, j);
         }
-        const f32x16 VF = transpose_mfma(rop(VRp[rb], 0), rop(VRp[rb], 1), eye);
-        const f32x16 OF = transpose_mfma(rop(ORp[rb], 0), rop(ORp[rb], 1), eye);
+        __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
+        stage_r(S + SV * MAT, hb, rop(VRp[rb], 0), rop(VRp[rb], 1), lr, h);
+        stage_r(S + SO * MAT, hb, rop(ORp[rb], 0), rop(ORp[rb], 1), lr, h);
 #pragma unroll
-        for (int s = 0; s < ST; ++s) { VFb[rb][s] = cvt8(VF, s); OFb[rb][s] = cvt8(OF, s); }
+        for (int s = 0; s < ST; ++s) {
+          VFb[rb][s] = tr_op(S + SV * MAT, thb + 1024 * s);
+          OFb[rb][s] = tr_op(S + SO * MAT, thb + 1024 * s);
+        }
       }
     }
-    f32x16 dQR[2], dKR[2], dVR[2], AOF[2];
+    // dQ, dK, dV and O row-major (lane -> row, values -> features), accumulated over heads with
+    // the feature-major operands masked to the head; the key-major P and dS of a (query block,
+    // key block) pair through this wave's half of the dQ and dK staging slots of block 2 cp
+    // (free until the staging after the head loop)
+    __bf16* const PS = stg + (2 * cp) * NSTAGE * MAT + SQ * MAT;
+    __bf16* const DS = stg + (2 * cp) * NSTAGE * MAT + SK * MAT;
+    f32x16 dQR[2], dKR[2], dVR[2], AOR[2];
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) dQR[rb] = dKR[rb] = dVR[rb] = AOF[rb] = f32x16{};
+    for (int rb = 0; rb < 2; ++rb) dQR[rb] = dKR[rb] = dVR[rb] = AOR[rb] = f32x16{};
 #pragma unroll
     for (int j = 0; j < HPB; ++j) {
       const bool mine = (lr / DH) == j;
@@ -700,12 +690,16 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           bf16x8 Pq[ST], Sq[ST];
 #pragma unroll
           for (int s = 0; s < ST; ++s) { Pq[s] = cvt8(sq[kb], s); Sq[s] = cvt8(dpq[kb], s); }
-          const f32x16 pk = transpose_mfma(Pq[0], Pq[1], eye), sk2 = transpose_mfma(Sq[0], Sq[1], eye);
+          stage_r(PS, hb, Pq[0], Pq[1], lr, h);
+          stage_r(DS, hb, Sq[0], Sq[1], lr, h);
 #pragma unroll
           for (int s = 0; s < ST; ++s) {
-            const bf16x8 Pk = cvt8(pk, s), Sk = cvt8(sk2, s);
-            AOF[qb] = mfma16(Pq[s], mine ? VFb[kb][s] : z, AOF[qb]);  // O[q][f]  += P[q][k] V[k][f]
+            AOR[qb] = mfma16(mine ? VFb[kb][s] : z, Pq[s], AOR[qb]);  // O[q][f]  += P[q][k] V[k][f]
             dQR[qb] = mfma16(mine ? KFb[kb][s] : z, Sq[s], dQR[qb]);  // dQ[q][f] += dS[q][k] K[k][f]
+          }
+#pragma unroll
+          for (int s = 0; s < ST; ++s) {
+            const bf16x8 Pk = tr_op(PS, thb + 1024 * s), Sk = tr_op(DS, thb + 1024 * s);
             dKR[kb] = mfma16(mine ? QFb[qb][s] : z, Sk, dKR[kb]);     // dK[k][f] += dS[q][k] Q[q][f]
             dVR[kb] = mfma16(mine ? OFb[qb][s] : z, Pk, dVR[kb]);     // dV[k][f] += P[q][k] dO[q][f]
           }
@@ -721,11 +715,10 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
       for (int r = 0; r < 16; ++r) { dKR[rb][r] *= isc; dVR[rb][r] *= sdh; }
 #pragma unroll
       for (int s = 0; s < ST; ++s) { dq[rb][s] = cvt8(dQR[rb], s); dk[rb][s] = cvt8(dKR[rb], s); dv[rb][s] = cvt8(dVR[rb], s); }
-      stage_ops(S + SQ * MAT, 32 * hb, dq[rb][0], dq[rb][1], eye, lr, h);
-      stage_ops(S + SK * MAT, 32 * hb, dk[rb][0], dk[rb][1], eye, lr, h);
-      stage_ops(S + SV * MAT, 32 * hb, dv[rb][0], dv[rb][1], eye, lr, h);
-#pragma unroll
-      for (int s = 0; s < ST; ++s) *reinterpret_cast<bf16x8*>(S + SO * MAT + soff(32 * hb + lr, 2 * s + h)) = cvt8(AOF[rb], s);
+      stage_r(S + SQ * MAT, hb, dq[rb][0], dq[rb][1], lr, h);
+      stage_r(S + SK * MAT, hb, dk[rb][0], dk[rb][1], lr, h);
+      stage_r(S + SV * MAT, hb, dv[rb][0], dv[rb][1], lr, h);
+      stage_r(S + SO * MAT, hb, cvt8(AOR[rb], 0), cvt8(AOR[rb], 1), lr, h);
     }
     // dx (as in the kernel above): head block 0 leaves g + its terms in LDS, head block 1 adds
     auto dx_terms = [&](int rb, int ob) {
@@ -793,8 +786,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           bf16x8 av[NB], bv[NB];
 #pragma unroll
           for (int i = 0; i < NB; ++i) {
-            av[i] = ld8(A + soff(32 * i + lr, 2 * s + h));
-            bv[i] = ld8(B + soff(32 * i + lr, 2 * s + h));
+            av[i] = tr_op(A, tb[i] + 1024 * s);
+            bv[i] = tr_op(B, tb[i] + 1024 * s);
           }
 #pragma unroll
           for (int i = 0; i < NB; ++i)

@@ -58,17 +58,33 @@ __device__ __forceinline__ f32x16 transpose_mfma(const bf16x8& x0, const bf16x8&
   return mfma16(x1, eye[1], mfma16(x0, eye[0], f32x16{}));
 }
 
+// Tiles of the 8-wave kernel: 64 BF16 columns per row (128 bytes, no padding) in perm16 order,
+// 8 units of 16 bytes; unit u of row r sits at position u ^ f(r), f(r) = (bit 1 of r, bit 2 of
+// r, bit 0 xor bit 3 of r) as bits (2, 1, 0).  Measured on gfx950 (bank-conflict counter of an
+// LDS probe): 16-byte writes serve 8 lanes per cycle over 128 bytes, 16-byte reads 16 lanes
+// and transposing reads 32 lanes per cycle over 64 banks of 4 bytes; with f, the 8 rows of a
+// write phase, the 16 rows of a read phase and the 4 rows x 2 column halves of a transposing
+// read phase all fall on distinct banks.
+constexpr int XR = 64;  // row stride (bf16)
+__device__ __forceinline__ int usw(int u, int row) {
+  return u ^ ((((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1) | ((row ^ (row >> 3)) & 1));
+}
 // gfx950's transposing LDS read (ds_read_b64_tr_b16): within each group of 16 lanes, lane
 // 4t + u supplies the address of 4 consecutive BF16 values and lane 4u + c receives, as its
-// value t, value c of lane 4t + u.  On a tile stored as rows of 4-column chunks (the perm16
-// order keeps each chunk contiguous), two such reads give lane l column l % 32 at 8 rows:
-// the row-contraction operand of the tile, with no transpose on the matrix cores.  p points
-// at (first row, first column) of the 32 x 32 part read; off is the lane's offset (toff).
-__device__ __forceinline__ bf16x8 tr_op(const __bf16* p, int off) {
+// value t, value c of lane 4t + u.  Two such reads give lane l column 32 cb + l % 32 at 8 rows
+// (values 4 rd + t from row 8 rd + 4 (l / 32) + t of the 16-row part at p): the row-
+// contraction operand of the tile, with no transpose on the matrix cores.  off[rd] is the
+// lane's offset for rows 8 rd + ... (mlp_toff); f depends on row bit 3, so the two reads have
+// offsets of their own.
+__device__ __forceinline__ int mlp_toff(int rd, int cb, int lane) {
+  const int g = lane >> 4, u = lane & 3, row = 8 * rd + 4 * (lane >> 5) + ((lane & 15) >> 2);
+  return row * XR + usw(4 * cb + 2 * (g & 1) + (u & 1), row) * 8 + 4 * (u >> 1);
+}
+__device__ __forceinline__ bf16x8 tr_op(const __bf16* p, const int (&off)[2]) {
   typedef short s16x8 __attribute__((ext_vector_type(8)));
   typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
-  const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + off));
-  const s16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + off + 8 * XS));
+  const s16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + off[0]));
+  const s16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + off[1]));
   return __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7));
 }
 
@@ -349,10 +365,10 @@ template <bool SEEDS>
 __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
   constexpr int M = 256, D = 64, NB = 2, DUS = M + 8;
   extern __shared__ __align__(16) char smem[];
-  __bf16* XA = reinterpret_cast<__bf16*>(smem);  // [RT][XS]   x, row-major (features in perm16 order)
-  __bf16* GA = XA + RT * XS;                      // [RT][XS]   g, row-major
-  __bf16* DT = GA + RT * XS;                      // [M][XS]    du, (hidden x row), rows in perm16 order
-  __bf16* W1s = DT + M * XS;                      // [D][DUS]   W1 (operand of dx = du W1^T), hidden in perm16 order
+  __bf16* XA = reinterpret_cast<__bf16*>(smem);  // [RT][XR]   x, row-major (features in perm16 order, usw units)
+  __bf16* GA = XA + RT * XR;                      // [RT][XR]   g, row-major
+  __bf16* DT = GA + RT * XR;                      // [M][XR]    du, (hidden x row), rows in perm16 order
+  __bf16* W1s = DT + M * XR;                      // [D][DUS]   W1 (operand of dx = du W1^T), hidden in perm16 order
   float* db2s = reinterpret_cast<float*>(W1s + D * DUS);     // [2 blocks of the tile][D]
   float4* GF = reinterpret_cast<float4*>(db2s + 2 * D);      // [4 roles][4][64]: g in FP32
   float4* XD = GF + 4 * 4 * 64;                              // [4 tiles][4][64]: dx over hidden [128, 256)
@@ -381,10 +397,12 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
   for (int i = t; i < D * M; i += 512) W1s[(i / M) * DUS + perm16(i % M)] = (__bf16)a.w1[i];
   if constexpr (SEEDS)
     for (int i = t; i < D; i += 512) hws[i] = i < a.d_real ? make_float2(a.head_w[2 * i], a.head_w[2 * i + 1]) : make_float2(0.f, 0.f);
-  // this lane's transposing-read offset (see tr_op) at row 4 h + t of a 64-wide perm16 tile:
-  // rows 32 rb + 16 s + 8 rd + 4 h + t (= 32 rb + tile_idx(8 s + 4 rd + t, h)) and 4 columns
-  // 32 fb + 16 (g & 1) + 4 u add constants (with g = lane / 16, t = lane % 16 / 4, u = lane % 4)
-  const int toff = (4 * h + ((lane & 15) >> 2)) * XS + 16 * ((lane >> 4) & 1) + 8 * (lane & 1) + 4 * ((lane >> 1) & 1);
+  // this lane's transposing-read offsets (see tr_op): rows 8 rd + 4 h + t of a 16-row part, i.e.
+  // rows 32 rb + tile_idx(8 s + 4 rd + t, h) of the tile with the part at row 32 rb + 16 s
+  const int toff[2][2] = {{mlp_toff(0, 0, lane), mlp_toff(1, 0, lane)}, {mlp_toff(0, 1, lane), mlp_toff(1, 1, lane)}};
+  // unit positions of this lane's row (rows 32 k + lr all share usw): 16-byte unit u = c / 8 + h
+  // with c a multiple of 16 sits at element (c ^ G8) of the row
+  int G8 = usw(h, lr) * 8;
   __syncthreads();  // W1s and the head weights initialised before any use
   const float bias = a.b1[hid];
 
@@ -402,14 +420,18 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
   auto fetch = [&](int64_t tl) {
     const int64_t g = 2 * tl + sb;
     const bool ok = tl < ntile && g < nblk;
+    // 32 x the lane id, formed here from the hardware's lane count (three instructions) rather
+    // than held in a register across the tile loop
+    int lo;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0\n\tv_lshlrev_b32 %0, 5, %0" : "=v"(lo));
     if (!gw) {
       const auto rx = rsrc(reinterpret_cast<const __bf16*>(a.save_mid) + (g * NB + sob) * 64 * 16, ok ? 64 * 16 * 2 : 0);
-      xn[0] = rld8(rx, lane * 32);
-      xn[1] = rld8(rx, lane * 32 + 16);
+      xn[0] = rld8(rx, lo);
+      xn[1] = rld8(rx, lo, 16);
     } else if constexpr (!SEEDS) {
       const auto rg = rsrc(a.g_in + (g * NB + sob) * 64 * 16, ok ? 64 * 16 * 4 : 0);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) gn[k] = rld4(rg, lane * 64 + 16 * k);
+      for (int k = 0; k < 4; ++k) gn[k] = rld4(rg, 2 * lo, 16 * k);
     } else {
       int64_t e;
       int pass, ric;
@@ -429,12 +451,15 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
   }
 
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    // G8 made opaque here: the XOR offsets below are formed in the loop, one instruction each,
+    // instead of being held in registers across it
+    asm volatile("" : "+v"(G8));
     const int64_t gb = 2 * tile + sb;  // block of this wave's role
     // ---- 1. stage x (waves 0-3) or g (waves 4-7): row-major and transposed, 16-byte writes;
     // value t of operand s is feature 32 sob + tile_idx(8 s + t, h), position 32 sob + 16 s + 8 h + t
     if (!gw) {
 #pragma unroll
-      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(XA + srow * XS + 32 * sob + 16 * s + 8 * h) = xn[s];
+      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(XA + srow * XR + ((32 * sob + 16 * s) ^ G8)) = xn[s];
     } else {
       float g[16];
       if constexpr (SEEDS) {
@@ -459,7 +484,7 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) GF[(q * 4 + k) * 64 + lane] = make_float4(g[4 * k], g[4 * k + 1], g[4 * k + 2], g[4 * k + 3]);
 #pragma unroll
-      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(GA + srow * XS + 32 * sob + 16 * s + 8 * h) = go[s];
+      for (int s = 0; s < 2; ++s) *reinterpret_cast<bf16x8*>(GA + srow * XR + ((32 * sob + 16 * s) ^ G8)) = go[s];
     }
     barrier_lds();
     fetch(tile + gridDim.x);
@@ -472,8 +497,8 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
       for (int r = 0; r < 16; ++r) u[r] = bias;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const bf16x8 xa = ld8(XA + (32 * rb + lr) * XS + 16 * s + 8 * h);
-        const bf16x8 ga = ld8(GA + (32 * rb + lr) * XS + 16 * s + 8 * h);
+        const bf16x8 xa = ld8(XA + (32 * rb + lr) * XR + ((16 * s) ^ G8));
+        const bf16x8 ga = ld8(GA + (32 * rb + lr) * XR + ((16 * s) ^ G8));
         u = mfma16(xa, w1b[s], u);  // (row x hidden): lane -> hidden, values -> rows
         dh = mfma16(ga, w2b[s], dh);
       }
@@ -487,15 +512,14 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
       }
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        const int pos = 32 * rb + 16 * s + 8 * h;
         const bf16x8 duo = cvt8(dh, s), ho = cvt8(u, s);
         // du as (hidden x row): one 16-byte write per lane, the layout x and g are staged in
-        *reinterpret_cast<bf16x8*>(DT + hid * XS + pos) = duo;
-        const int ro = (32 * rb + 16 * s) * XS;
+        *reinterpret_cast<bf16x8*>(DT + hid * XR + ((32 * rb + 16 * s) ^ G8)) = duo;
+        const int ro = (32 * rb + 16 * s) * XR;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-          dW1[i] = mfma16(tr_op(XA + ro + 32 * i, toff), duo, dW1[i]);  // (in x hidden)
-          dW2[i] = mfma16(ho, tr_op(GA + ro + 32 * i, toff), dW2[i]);   // (hidden x out)
+          dW1[i] = mfma16(tr_op(XA + ro, toff[i]), duo, dW1[i]);  // (in x hidden)
+          dW2[i] = mfma16(ho, tr_op(GA + ro, toff[i]), dW2[i]);   // (hidden x out)
         }
       }
     }
@@ -507,7 +531,7 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
 #pragma unroll
     for (int s = 0; s < (M / 16) / 2; ++s)  // A[m = in][k = hidden] = W1, B[k = hidden][n = row] = du
       acc = mfma16(ld8(W1s + (32 * sob + lr) * DUS + 16 * (k0 + s) + 8 * h),
-                   tr_op(DT + 16 * (k0 + s) * XS + 32 * sb, toff), acc);
+                   tr_op(DT + 16 * (k0 + s) * XR, toff[sb]), acc);
     if (!gw) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -554,7 +578,7 @@ __global__ void __launch_bounds__(512) k_bwd_mlp8_bf16(BwdArgs a) {
 }
 
 size_t bwd_mlp8_bf16_lds() {
-  return (size_t)(2 * RT * XS + 256 * XS + 64 * (256 + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float) +
+  return (size_t)(2 * RT * XR + 256 * XR + 64 * (256 + 8)) * sizeof(__bf16) + 2 * 64 * sizeof(float) +
          2 * 4 * 4 * 64 * sizeof(float4) + 64 * sizeof(float2);
 }
 

@@ -2,15 +2,20 @@
 read (ds_read_b64_tr_b16).  The address formulas of the kernels are restated here and checked
 for (1) the transpose identity: a tile staged from its row-major MFMA operands and read back
 with the transposing read gives the feature-major operand in the row order the products
-expect, and (2) no LDS bank conflicts inside one access phase (64 banks of 4 bytes; 8 lanes
-per phase of a 16-byte access, 16 lanes per phase of an 8-byte access).
+expect, and (2) no LDS bank conflicts inside one access phase.
 
-Lane mapping of the transposing read, as measured on the device with an in-bounds probe: in
-each group of 16 lanes, lane 4t + u supplies the address of 4 consecutive 16-bit values and
-lane 4u + c receives value c of lane 4t + u as its value t."""
+Device facts the model uses, both measured on gfx950 with in-bounds LDS probes:
+* lane mapping of the transposing read: in each group of 16 lanes, lane 4t + u supplies the
+  address of 4 consecutive 16-bit values and lane 4u + c receives value c of lane 4t + u as
+  its value t;
+* access phases (from the bank-conflict counter on patterns that are conflict-free under one
+  model and not under the others): 8-byte and transposing reads serve 32 consecutive lanes
+  per cycle and 16-byte reads 16 lanes, over 64 banks of 4 bytes; 16-byte writes serve 8
+  lanes per cycle over 128 bytes (32 banks)."""
 import itertools
 
 BANKS = 64
+READ_TR_LANES, READ16_LANES, WRITE16_LANES, WRITE_BANKS = 32, 16, 8, 32
 
 
 def tile_idx(r, h):
@@ -27,20 +32,24 @@ def tr_read(addr_of_lane, mem):
     return out
 
 
-def conflict_free(addrs_bytes, width):
+def conflict_free(addrs_bytes, width, banks=BANKS):
     """One access phase: every lane's `width` bytes on banks no other lane of the phase uses."""
     used = set()
     for a in addrs_bytes:
         for b in range(a // 4, (a + width) // 4):
-            if b % BANKS in used:
+            if b % banks in used:
                 return False
-            used.add(b % BANKS)
+            used.add(b % banks)
     return True
+
+
+def phases(addr_of_lane, lanes_per_phase):
+    return [[addr_of_lane(lane) for lane in range(p, p + lanes_per_phase)] for p in range(0, 64, lanes_per_phase)]
 
 
 # ---------------------------------------------------------------- attention backward (n <= 32)
 def rsw(u, row):
-    return (u & 4) | ((u & 3) ^ ((((row >> 1) & 1) << 1) | ((row >> 2) & 1)))
+    return u ^ ((((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1) | (row & 1))
 
 
 def stage_r_addr(fb, s, lr, h):
@@ -48,14 +57,14 @@ def stage_r_addr(fb, s, lr, h):
     return lr * 64 + rsw(4 * fb + 2 * s + h, lr) * 8
 
 
-def tr_off(row, lane):
+def tr_off(row, fb, lane):
     g, u = lane >> 4, lane & 3
-    return row * 64 + rsw(2 * (g & 1) + (u & 1), row) * 8 + 4 * (u >> 1)
+    return row * 64 + rsw(4 * fb + 2 * (g & 1) + (u & 1), row) * 8 + 4 * (u >> 1)
 
 
-def toff(lane):
+def toff(lane, fb):
     h = lane >> 5
-    return tr_off(4 * h + ((lane & 15) >> 2), lane)
+    return tr_off(4 * h + ((lane & 15) >> 2), fb, lane)
 
 
 def test_attention_staging_transposes():
@@ -69,7 +78,7 @@ def test_attention_staging_transposes():
         for s in range(2):
             got = {}
             for rd in range(2):
-                off = lambda lane, rd=rd: toff(lane) + (16 * s + 8 * rd) * 64 + 32 * fb
+                off = lambda lane, rd=rd: toff(lane, fb) + (16 * s + 8 * rd) * 64
                 for lane, vals in tr_read(off, mem).items():
                     got.setdefault(lane, []).extend(vals)
             for lane, vals in got.items():
@@ -79,13 +88,11 @@ def test_attention_staging_transposes():
 
 def test_attention_staging_conflict_free():
     for fb, s in itertools.product(range(2), range(2)):
-        lanes = [(lane & 31, lane >> 5) for lane in range(64)]
-        for p in range(8):  # 16-byte writes: 8 lanes per phase
-            assert conflict_free([2 * stage_r_addr(fb, s, lr, h) for lr, h in lanes[8 * p: 8 * p + 8]], 16)
+        for ph in phases(lambda lane: 2 * stage_r_addr(fb, s, lane & 31, lane >> 5), WRITE16_LANES):
+            assert conflict_free(ph, 16, WRITE_BANKS)
     for s, rd, fb in itertools.product(range(2), range(2), range(2)):
-        for g in range(4):  # 8-byte transposing reads: 16 lanes per phase
-            addrs = [2 * (toff(lane) + (16 * s + 8 * rd) * 64 + 32 * fb) for lane in range(16 * g, 16 * g + 16)]
-            assert conflict_free(addrs, 8)
+        for ph in phases(lambda lane: 2 * (toff(lane, fb) + (16 * s + 8 * rd) * 64), READ_TR_LANES):
+            assert conflict_free(ph, 8)
 
 
 def test_attention_staging_halves_disjoint():
@@ -96,38 +103,61 @@ def test_attention_staging_halves_disjoint():
 
 
 # ---------------------------------------------------------------- feed-forward backward (8 waves)
-XS = 72  # row stride of the 64-wide tiles
+XR = 64  # row stride of the 64-wide tiles of the 8-wave feed-forward backward
 
 
-def mlp_toff(lane):
-    h = lane >> 5
-    return (4 * h + ((lane & 15) >> 2)) * XS + 16 * ((lane >> 4) & 1) + 8 * (lane & 1) + 4 * ((lane >> 1) & 1)
+def usw(u, row):
+    return u ^ ((((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1) | ((row ^ (row >> 3)) & 1))
+
+
+def mlp_toff(rd, cb, lane):
+    g, u = lane >> 4, lane & 3
+    row = 8 * rd + 4 * (lane >> 5) + ((lane & 15) >> 2)
+    return row * XR + usw(4 * cb + 2 * (g & 1) + (u & 1), row) * 8 + 4 * (u >> 1)
+
+
+def g8(lane):
+    """The kernel's G8: unit offset (c ^ G8) of a 16-byte unit c / 8 + h of row lr (and of rows 32 k + lr)."""
+    return usw(lane >> 5, lane & 31) * 8
+
+
+def test_mlp_unit_offset_matches_swizzle():
+    for lane, c in itertools.product(range(64), range(0, 64, 16)):
+        lr, h = lane & 31, lane >> 5
+        for row in (lr, 32 + lr):
+            assert (c ^ g8(lane)) == usw(c // 8 + h, row) * 8
 
 
 def test_mlp_tiles_transpose():
-    # x staged row-major: row r, position 32 sob + 16 s + 8 h + t holds feature 32 sob + tile_idx(8 s + t, h)
+    # x staged row-major: row r, unit 4 sob + 2 s + h holds operand s of lane half h of feature block sob
     mem = {}
     for r, sob, s, h, t in itertools.product(range(64), range(2), range(2), range(2), range(8)):
-        mem[r * XS + 32 * sob + 16 * s + 8 * h + t] = (r, 32 * sob + tile_idx(8 * s + t, h))
+        mem[r * XR + usw(4 * sob + 2 * s + h, r) * 8 + t] = (r, 32 * sob + tile_idx(8 * s + t, h))
+    assert len(mem) == 64 * 64
     for rb, s, i in itertools.product(range(2), range(2), range(2)):
         got = {}
         for rd in range(2):
-            off = lambda lane, rd=rd: mlp_toff(lane) + (32 * rb + 16 * s) * XS + 32 * i + 8 * rd * XS
+            off = lambda lane, rd=rd: mlp_toff(rd, i, lane) + (32 * rb + 16 * s) * XR
             for lane, vals in tr_read(off, mem).items():
                 got.setdefault(lane, []).extend(vals)
         for lane, vals in got.items():
             h = lane >> 5
             assert vals == [(32 * rb + tile_idx(8 * s + t, h), 32 * i + lane % 32) for t in range(8)]
+    # the row-major operand reads of the feature contractions: row 32 rb + lr, unit 2 s + h, s = 0..3
+    for rb, s, lane in itertools.product(range(2), range(4), range(64)):
+        lr, h = lane & 31, lane >> 5
+        base = (32 * rb + lr) * XR + ((16 * s) ^ g8(lane))
+        assert [mem[base + t] for t in range(8)] == [(32 * rb + lr, tile_idx(8 * s + t, h)) for t in range(8)]
 
 
 def test_mlp_tiles_conflict_free():
-    for base in (0, 16 * XS, 32 * XS + 32):
+    for rb, s, i in itertools.product(range(2), range(2), range(2)):  # transposing reads of x, g (and du)
         for rd in range(2):
-            for g in range(4):
-                addrs = [2 * (mlp_toff(lane) + base + 8 * rd * XS) for lane in range(16 * g, 16 * g + 16)]
-                assert conflict_free(addrs, 8)
-    # du written as (hidden x row): lane (hidden 32 w + lr, h) writes 16 bytes at row position 32 rb + 16 s + 8 h
-    for rb, s in itertools.product(range(2), range(2)):
-        lanes = [(lane & 31, lane >> 5) for lane in range(64)]
-        for p in range(8):
-            assert conflict_free([2 * (lr * XS + 32 * rb + 16 * s + 8 * h) for lr, h in lanes[8 * p: 8 * p + 8]], 16)
+            for ph in phases(lambda lane: 2 * (mlp_toff(rd, i, lane) + (32 * rb + 16 * s) * XR), READ_TR_LANES):
+                assert conflict_free(ph, 8)
+    for rb, s in itertools.product(range(2), range(4)):  # 16-byte row reads
+        for ph in phases(lambda lane: 2 * ((32 * rb + (lane & 31)) * XR + ((16 * s) ^ g8(lane))), READ16_LANES):
+            assert conflict_free(ph, 16)
+    for k, c in itertools.product(range(8), range(0, 64, 16)):  # 16-byte writes of rows 32 k + lr (x, g, du)
+        for ph in phases(lambda lane: 2 * ((32 * k + (lane & 31)) * XR + (c ^ g8(lane))), WRITE16_LANES):
+            assert conflict_free(ph, 16, WRITE_BANKS)
