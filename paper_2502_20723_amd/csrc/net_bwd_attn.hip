@@ -12,10 +12,10 @@
 // weights) walks tiles of 4 blocks of 32 rows; wave w handles head block w / 4
 // (attention features [32 (w/4), 32 (w/4) + 32)) of block w % 4 of the tile,
 // then owns rows [32 (w/4), 32 (w/4) + 32) of one weight gradient (w % 4 = 0..3:
-// Wq, Wk, Wv, W_O) accumulated in registers for the whole launch.  The two waves
-// of a block add their dx terms in turn through LDS: head block 0 leaves its terms
-// in the exchange area before the workgroup barrier, head block 1 adds g and its own
-// terms after it and writes dx.
+// Wq, Wk, Wv, W_O) accumulated in registers for the whole launch.  After the
+// workgroup barrier that follows the staging, the wave of head block hb forms dx for
+// output features [32 hb, 32 hb + 32), reading the other head block's dQ, dK, dV from
+// the staging.
 //
 // Block phase (one wave per head block).  Every contraction over keys or queries needs its
 // operands with lanes enumerating features and values enumerating rows, the
@@ -107,7 +107,6 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
   extern __shared__ __align__(16) char smem[];
   __bf16* Wl = reinterpret_cast<__bf16*>(smem);      // Wq, Wk, Wv, W_O^T fragments [4][D*D]
   __bf16* stg = Wl + 4 * D * D;                       // [4 blocks][NSTAGE][MAT]
-  float4* xch = reinterpret_cast<float4*>(stg + 4 * NSTAGE * MAT);  // [4 blocks][NB][4][64]: g + head block 0's dx terms
 
   const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform (scalar branches below)
@@ -382,59 +381,60 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     stage_r(S + SK * MAT, hb, dk[0], dk[1], lr, h);
     stage_r(S + SV * MAT, hb, dv[0], dv[1], lr, h);
     stage_r(S + SO * MAT, hb, __builtin_bit_cast(bf16x8, ow[0]), __builtin_bit_cast(bf16x8, ow[1]), lr, h);
-    // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T.  The wave of head block 0 leaves its terms in LDS;
-    // after the barrier the wave of head block 1 adds g and its own terms and writes dx (lane l
-    // of both waves holds the same rows and features).  g is loaded by head block 1 before the
-    // barrier, where that wave waits for the other one anyway: the load is off the critical path.
-    auto dx_terms = [&](int ob) {
+    // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T, output feature block hb from this wave: after the
+    // barrier it reads the other head block's dQ, dK, dV from the staging (the 16-byte operands
+    // that wave staged) and sums (g + terms of attention block 0) + terms of attention block 1.
+    // g is loaded before the barrier, where the wave may wait for the other waves.
+    auto dx_terms = [&](int ib, const bf16x8 (&q)[ST], const bf16x8 (&k)[ST], const bf16x8 (&v)[ST]) {
       f32x16 acc = {};
-      const int voff = (hb * ST * 64 + lane) * 16;  // fragment ((ob NB + hb) ST + s) of each matrix
+      const int voff = (ib * ST * 64 + lane) * 16;  // fragment ((hb NB + ib) ST + s) of each matrix
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
-        const int so = (ob * NB * ST + s) * 64 * 16;
-        acc = mfma16(rld8(WT, voff, so), dq[s], acc);
-        acc = mfma16(rld8(WT, voff, so + D * D * 2), dk[s], acc);
-        acc = mfma16(rld8(WT, voff, so + 2 * D * D * 2), dv[s], acc);
+        const int so = (hb * NB * ST + s) * 64 * 16;
+        acc = mfma16(rld8(WT, voff, so), q[s], acc);
+        acc = mfma16(rld8(WT, voff, so + D * D * 2), k[s], acc);
+        acc = mfma16(rld8(WT, voff, so + 2 * D * D * 2), v[s], acc);
       }
       return acc;
     };
-    float4* X = xch + bw * NB * 4 * 64;
     // the block's g and dx through buffer resources at the block (a wave-uniform base and one
     // lane offset, instead of 64-bit addresses per lane kept live across the tile loop); empty
     // past the last block
     constexpr uint32_t BLK_BYTES = NB * 64 * 16 * sizeof(float);
     const auto gres = rsrc(a.g_in + (valid ? gb : 0) * NB * 64 * 16, valid ? BLK_BYTES : 0);
     const auto dres = rsrc(a.g_out + (valid ? gb : 0) * NB * 64 * 16, valid ? BLK_BYTES : 0);
-    float4 sv[NB][4];
-    if (hb == 0 && valid) {
+    float4 sv[4];
 #pragma unroll
-      for (int ob = 0; ob < NB; ++ob) {
-        const f32x16 acc = dx_terms(ob);
+    for (int q = 0; q < 4; ++q) sv[q] = rld4(gres, lane * 64, hb * 64 * 64 + 16 * q);
+    barrier_lds();  // staging of both head blocks in LDS
+    if (valid) {
+      bf16x8 oq[ST], ok[ST], ov[ST];  // the other head block's operands, as it staged them
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          X[(ob * 4 + q) * 64 + lane] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+      for (int s = 0; s < ST; ++s) {
+        const int e = lr * 64 + rsw(4 * (hb ^ 1) + 2 * s + h, lr) * 8;
+        oq[s] = ld8(S + SQ * MAT + e);
+        ok[s] = ld8(S + SK * MAT + e);
+        ov[s] = ld8(S + SV * MAT + e);
       }
-    } else if (hb == 1) {
-#pragma unroll
-      for (int ob = 0; ob < NB; ++ob)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) sv[ob][q] = rld4(gres, lane * 64, ob * 64 * 64 + 16 * q);
-    }
-    barrier_lds();  // staging and head block 0's part of dx in LDS
-    if (hb == 1 && valid) {
-#pragma unroll
-      for (int ob = 0; ob < NB; ++ob) {
-        const f32x16 acc = dx_terms(ob);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 v = X[(ob * 4 + q) * 64 + lane];
-          const float4 g = sv[ob][q];
-          rst4(dres, lane * 64,
-               make_float4((g.x + v.x) + acc[4 * q], (g.y + v.y) + acc[4 * q + 1], (g.z + v.z) + acc[4 * q + 2],
-                           (g.w + v.w) + acc[4 * q + 3]),
-               ob * 64 * 64 + 16 * q);
-        }
+      f32x16 a0, a1;
+      if (hb == 0) {
+        a0 = dx_terms(0, dq, dk, dv);
+        a1 = dx_terms(1, oq, ok, ov);
+      } else {
+        a0 = dx_terms(0, oq, ok, ov);
+        a1 = dx_terms(1, dq, dk, dv);
       }
+      // all four results formed before the first store: the stores' data registers are then not
+      // rewritten by the vector ALU right behind the store that reads them
+      float4 o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 g = sv[q];
+        o[q] = make_float4((g.x + a0[4 * q]) + a1[4 * q], (g.y + a0[4 * q + 1]) + a1[4 * q + 1],
+                           (g.z + a0[4 * q + 2]) + a1[4 * q + 2], (g.w + a0[4 * q + 3]) + a1[4 * q + 3]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rst4(dres, lane * 64, o[q], hb * 64 * 64 + 16 * q);
     }
     // issued after the dx step, whose loads would otherwise wait behind these in the in-order load counter
     fetch(tile + gridDim.x);
