@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
 // block w % 2 of configuration-pass w / 2 over both of its blocks: score, P and dS tiles are
 // 2 x 2 (query block x key block), P comes from the forward's normalisers, dK and dV of a
 // key block sum over both query blocks.  Staging, the transposes through the transposing
-// LDS read, the dx exchange through LDS and the per-wave weight gradients (wave w owns all
+// LDS read, dx by output feature block and the per-wave weight gradients (wave w owns all
 // of Wq, Wk, Wv, W_O for w = 0..3) are those of the kernel above with 4 waves; the products
 // keep feature-major operands masked per head (fresh accumulators per head would not fit
 // next to the 2 x 2 tiles).  Padding rows add nothing: their keys have P = 0 and their
@@ -485,7 +485,6 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
   extern __shared__ __align__(16) char smem[];
   __bf16* Wl = reinterpret_cast<__bf16*>(smem);
   __bf16* stg = Wl + 4 * D * D;
-  float4* xch = reinterpret_cast<float4*>(stg + 4 * NSTAGE * MAT);  // [4 blocks][NB][4][64]
 
   const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -720,56 +719,59 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
       stage_r(S + SV * MAT, hb, dv[rb][0], dv[rb][1], lr, h);
       stage_r(S + SO * MAT, hb, cvt8(AOR[rb], 0), cvt8(AOR[rb], 1), lr, h);
     }
-    // dx (as in the kernel above): head block 0 leaves g + its terms in LDS, head block 1 adds
-    auto dx_terms = [&](int rb, int ob) {
+    // dx (as in the kernel above): output feature block hb from this wave, for both of its row
+    // blocks; the other head block's dQ, dK, dV are read back from the staging after the barrier
+    auto dx_terms = [&](int ib, const bf16x8 (&q)[ST], const bf16x8 (&k)[ST], const bf16x8 (&v)[ST]) {
       f32x16 acc = {};
-      const int voff = (hb * ST * 64 + lane) * 16;
+      const int voff = (ib * ST * 64 + lane) * 16;
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
-        const int so = (ob * NB * ST + s) * 64 * 16;
-        acc = mfma16(rld8(WT, voff, so), dq[rb][s], acc);
-        acc = mfma16(rld8(WT, voff, so + D * D * 2), dk[rb][s], acc);
-        acc = mfma16(rld8(WT, voff, so + 2 * D * D * 2), dv[rb][s], acc);
+        const int so = (hb * NB * ST + s) * 64 * 16;
+        acc = mfma16(rld8(WT, voff, so), q[s], acc);
+        acc = mfma16(rld8(WT, voff, so + D * D * 2), k[s], acc);
+        acc = mfma16(rld8(WT, voff, so + 2 * D * D * 2), v[s], acc);
       }
       return acc;
     };
-    if (hb == 0) {
+    float4 sv[2][4];
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const int64_t gb = 4 * tile + 2 * cp + rb;
-        float4* X = xch + (2 * cp + rb) * NB * 4 * 64;
-        float4 sv[NB][4];
+    for (int rb = 0; rb < 2; ++rb) {
+      const int64_t gb = 4 * tile + 2 * cp + rb;
 #pragma unroll
-        for (int ob = 0; ob < NB; ++ob)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) sv[ob][q] = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + ob) * 64 + lane) * 16)[q];
-#pragma unroll
-        for (int ob = 0; ob < NB; ++ob) {
-          const f32x16 acc = dx_terms(rb, ob);
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            X[(ob * 4 + q) * 64 + lane] = make_float4(sv[ob][q].x + acc[4 * q], sv[ob][q].y + acc[4 * q + 1],
-                                                       sv[ob][q].z + acc[4 * q + 2], sv[ob][q].w + acc[4 * q + 3]);
-        }
-      }
+      for (int q = 0; q < 4; ++q) sv[rb][q] = reinterpret_cast<const float4*>(a.g_in + ((gb * NB + hb) * 64 + lane) * 16)[q];
     }
-    barrier_lds();  // staging and head block 0's part of dx in LDS
-    if (hb == 1) {
+    barrier_lds();  // staging of both head blocks in LDS
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        const int64_t gb = 4 * tile + 2 * cp + rb;
-        const float4* X = xch + (2 * cp + rb) * NB * 4 * 64;
+    for (int rb = 0; rb < 2; ++rb) {
+      const int64_t gb = 4 * tile + 2 * cp + rb;
+      const __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
+      bf16x8 oq[ST], ok[ST], ov[ST];  // the other head block's operands, as it staged them
 #pragma unroll
-        for (int ob = 0; ob < NB; ++ob) {
-          const f32x16 acc = dx_terms(rb, ob);
-          float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + ob) * 64 + lane) * 16);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float4 v = X[(ob * 4 + q) * 64 + lane];
-            dst[q] = make_float4(v.x + acc[4 * q], v.y + acc[4 * q + 1], v.z + acc[4 * q + 2], v.w + acc[4 * q + 3]);
-          }
-        }
+      for (int s = 0; s < ST; ++s) {
+        const int e = lr * 64 + rsw(4 * (hb ^ 1) + 2 * s + h, lr) * 8;
+        oq[s] = ld8(S + SQ * MAT + e);
+        ok[s] = ld8(S + SK * MAT + e);
+        ov[s] = ld8(S + SV * MAT + e);
       }
+      f32x16 a0, a1;
+      if (hb == 0) {
+        a0 = dx_terms(0, dq[rb], dk[rb], dv[rb]);
+        a1 = dx_terms(1, oq, ok, ov);
+      } else {
+        a0 = dx_terms(0, oq, ok, ov);
+        a1 = dx_terms(1, dq[rb], dk[rb], dv[rb]);
+      }
+      // all four results formed before the first store (see the kernel above)
+      float4 o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 g = sv[rb][q];
+        o[q] = make_float4((g.x + a0[4 * q]) + a1[4 * q], (g.y + a0[4 * q + 1]) + a1[4 * q + 1],
+                           (g.z + a0[4 * q + 2]) + a1[4 * q + 2], (g.w + a0[4 * q + 3]) + a1[4 * q + 3]);
+      }
+      float4* dst = reinterpret_cast<float4*>(a.g_out + ((gb * NB + hb) * 64 + lane) * 16);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[q] = o[q];
     }
     fetch(tile + gridDim.x);
 
@@ -809,7 +811,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
 }
 
 size_t bwd_attn_bf16_lds() {
-  return (size_t)(4 * 64 * 64 + 4 * NSTAGE * MAT) * sizeof(__bf16) + 4 * 2 * 64 * 16 * sizeof(float);
+  return (size_t)(4 * 64 * 64 + 4 * NSTAGE * MAT) * sizeof(__bf16);
 }
 
 bool bwd_attn_bf16_supported(int d, int D, int DH, bool span) { return d == 64 && D == 64 && (DH == 8 || DH == 16); }
