@@ -8,14 +8,16 @@
 //   dQ = dS K, dK = dS^T Q, dV = P^T dO;  dx = g + dQ Wq^T + dK Wk^T + dV Wv^T;
 //   dW_O += O^T g, dWq += x^T dQ, dWk += x^T dK, dWv += x^T dV.
 //
-// Work decomposition.  A workgroup of 8 waves (two per SIMD, sharing the LDS
-// weights) walks tiles of 4 blocks of 32 rows; wave w handles head block w / 4
-// (attention features [32 (w/4), 32 (w/4) + 32)) of block w % 4 of the tile,
-// then owns rows [32 (w/4), 32 (w/4) + 32) of one weight gradient (w % 4 = 0..3:
-// Wq, Wk, Wv, W_O) accumulated in registers for the whole launch.  After the
-// workgroup barrier that follows the staging, the wave of head block hb forms dx for
-// output features [32 hb, 32 hb + 32), reading the other head block's dQ, dK, dV from
-// the staging.
+// Work decomposition.  A workgroup of 4 waves walks tiles of 2 blocks of 32 rows; wave w
+// handles head block w / 2 (attention features [32 (w/2), 32 (w/2) + 32)) of block w % 2 of
+// the tile, then owns one whole weight gradient (w = 0..3: Wq, Wk, Wv, W_O), accumulated in
+// registers for the whole launch.  Two such workgroups run on each CU (80 KB of LDS each), so
+// the two waves of a SIMD belong to different workgroups: their barriers are independent and
+// they drift into different phases of their tiles (one in the matrix-core-heavy projections
+// or gradient products while the other runs its softmax), which a single 8-wave workgroup
+// over 4 blocks, whose waves all meet at every barrier, did not allow.  After the workgroup
+// barrier that follows the staging, the wave of head block hb forms dx for output features
+// [32 hb, 32 hb + 32), reading the other head block's dQ, dK, dV from the staging.
 //
 // Block phase (one wave per head block).  Every contraction over keys or queries needs its
 // operands with lanes enumerating features and values enumerating rows, the
@@ -29,7 +31,7 @@
 // Gradient phase (all waves).  x, g, O, dQ, dK, dV of each block are staged
 // in LDS row-major (one 16-byte write per operand and lane, see stage_r), and read
 // back as row-contraction operands with the transposing read.  After a workgroup
-// barrier, wave w adds the tile's 4 x 32 rows into its gradient rows.  Each workgroup
+// barrier, wave w adds the tile's 2 x 32 rows into its gradient.  Each workgroup
 // writes its four gradients once per launch to its partial slot [4 D^2] (Wq, Wk, Wv as
 // (in, attention feature), W_O as (attention feature, out)); the slots are
 // summed in FP64 afterwards.
@@ -44,6 +46,7 @@ namespace tdo {
 namespace {
 
 constexpr int MAT = 64 * 32;  // one staged matrix: 32 rows x 64 features (BF16)
+constexpr int ATTN_BPT = 2;   // blocks of 32 rows a tile of the n <= 32 kernel (its workgroup: 2 BPT waves)
 enum { SX = 0, SG = 1, SQ = 2, SK = 3, SV = 4, SO = 5, NSTAGE = 6 };
 
 __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
@@ -63,9 +66,13 @@ __device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
 __device__ __forceinline__ int rsw(int u, int row) {
   return u ^ ((((row >> 1) & 1) << 2) | (((row >> 2) & 1) << 1) | (row & 1));
 }
-__device__ __forceinline__ void stage_r(__bf16* m, int fb, const bf16x8& o0, const bf16x8& o1, int lr, int h) {
-  *reinterpret_cast<bf16x8*>(m + lr * 64 + rsw(4 * fb + h, lr) * 8) = o0;
-  *reinterpret_cast<bf16x8*>(m + lr * 64 + rsw(4 * fb + 2 + h, lr) * 8) = o1;
+// The lane's part of its row's unit offsets: unit 4 fb + 2 s + h of row lr starts at element
+// rh ^ (32 fb + 16 s), rh = 64 lr | ((8 h) ^ 8 f(lr)) (the XOR acts on bits 3..5 only).  One
+// register for every staged write and row read of the lane, instead of one per unit.
+__device__ __forceinline__ int stage_rh(int lr, int h) { return lr * 64 | (rsw(h, lr) * 8); }
+__device__ __forceinline__ void stage_r(__bf16* m, int fb, const bf16x8& o0, const bf16x8& o1, int rh) {
+  *reinterpret_cast<bf16x8*>(m + (rh ^ (32 * fb))) = o0;
+  *reinterpret_cast<bf16x8*>(m + (rh ^ (32 * fb + 16))) = o1;
 }
 // ds_read_b64_tr_b16: within each group of 16 lanes, lane 4t + u supplies the address of 4
 // consecutive BF16 values and lane 4u + c receives, as its value t, value c of lane 4t + u.
@@ -101,22 +108,23 @@ __device__ __forceinline__ u32x2 neg_terms(float l) {
 
 }  // namespace
 
+// Two workgroups per CU (LDS 80 KB each, two waves per SIMD, one of each workgroup).
 template <int DH, bool MASKED>
-__global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
-  constexpr int D = 64, NB = 2, ST = 2, HPB = 32 / DH;
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_bwd_attn_bf16(BwdArgs a) {
+  constexpr int D = 64, NB = 2, ST = 2, HPB = 32 / DH, NT = 256, BPT = ATTN_BPT;
   extern __shared__ __align__(16) char smem[];
   __bf16* Wl = reinterpret_cast<__bf16*>(smem);      // Wq, Wk, Wv, W_O^T fragments [4][D*D]
-  __bf16* stg = Wl + 4 * D * D;                       // [4 blocks][NSTAGE][MAT]
+  __bf16* stg = Wl + 4 * D * D;                       // [BPT blocks][NSTAGE][MAT]
 
   const int t = threadIdx.x, lane = t & 63, h = lane >> 5, lr = lane & 31;
   const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave-uniform (scalar branches below)
-  const int bw = w & 3, hb = w >> 2;  // block of the tile, head block
+  const int bw = w & 1, hb = w >> 1;  // block of the tile, head block
   {
     const int4* sf = reinterpret_cast<const int4*>(a.wf);
     const int4* sb = reinterpret_cast<const int4*>(a.wb);
     int4* dl = reinterpret_cast<int4*>(Wl);
-    for (int i = t; i < 3 * D * D / 8; i += 512) dl[i] = sf[i];
-    for (int i = t; i < D * D / 8; i += 512) dl[3 * D * D / 8 + i] = sb[3 * D * D / 8 + i];
+    for (int i = t; i < 3 * D * D / 8; i += NT) dl[i] = sf[i];
+    for (int i = t; i < D * D / 8; i += NT) dl[3 * D * D / 8 + i] = sb[3 * D * D / 8 + i];
   }
   const __bf16 *Wq = Wl, *Wk = Wl + D * D, *Wv = Wl + 2 * D * D, *WoT = Wl + 3 * D * D;
   // Wq^T, Wk^T, Wv^T fragments [3][D*D] BF16 in global memory (L2-resident), read through a
@@ -128,7 +136,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
   const int64_t E = a.n_entries_dev ? *a.n_entries_dev : a.n_entries;
   const int n = a.n, cpb = a.cpb;
   const int64_t nblk = 2 * ((E + cpb - 1) / cpb);
-  const int64_t ntile = (nblk + 3) / 4;
+  const int64_t ntile = (nblk + BPT - 1) / BPT;
   const float sc = a.score_scale, isd = a.inv_sqrt_dh;
   // valid (query, key) pairs of this lane's row lr against rows tile_idx(r, h): same configuration
   // slot, slot < cpb (symmetric, so the same bits serve query-major and key-major tiles)
@@ -144,10 +152,13 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
   // products' K steps), 16 s rows on for operand s
   const int tb[2] = {tr_off(4 * h + ((lane & 15) >> 2), 0, lane), tr_off(4 * h + ((lane & 15) >> 2), 1, lane)};
   const int thb = hb ? tb[1] : tb[0];
+  int rh = stage_rh(lr, h);
 
-  f32x16 dW[NB];  // rows [32 hb, 32 hb + 32) of weight gradient bw
+  f32x16 dW[NB][NB];  // weight gradient w (Wq, Wk, Wv, W_O), all 64 x 64
 #pragma unroll
-  for (int j = 0; j < NB; ++j) dW[j] = f32x16{};
+  for (int k = 0; k < NB; ++k)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) dW[k][j] = f32x16{};
 
   // x (layer input, saved in BF16) and g (gradient of the sub-layer output) of block gb, lane ->
   // row, values -> features 32 ib + tile_idx(r, h); loaded one tile ahead, so that the
@@ -159,36 +170,40 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     // the block's saved normalisers, x and g through buffer resources at the block (scalar
     // bases and one lane offset each, no 64-bit addresses per lane); past the last block the
     // resources are empty and the loads return zeros
-    const int64_t g = 4 * tl + bw;
+    const int64_t g = (int64_t)BPT * tl + bw;
     const bool ok = tl < ntile && g < nblk;
     const int64_t gg = ok ? g : 0;
     const auto lres = rsrc(a.lse + gg * 32 * (NB * HPB), ok ? 32 * NB * HPB * 4 : 0);
     const auto xres = rsrc(reinterpret_cast<const __bf16*>(a.save_x) + gg * NB * 64 * 16, ok ? NB * 64 * 16 * 2 : 0);
     const auto gres = rsrc(a.g_in + gg * NB * 64 * 16, ok ? NB * 64 * 16 * 4 : 0);
+    // the lane offsets (lane * 32 for x, lane * 64 for g) formed here from the lane id, not kept
+    // in registers across the tile loop
+    int l32;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0\n\tv_lshlrev_b32 %0, 5, %0" : "=v"(l32));
     if constexpr (HPB == 4) {
-      // row lr's normalisers at lr * 32 bytes: the x offset lane * 32 with the lane half masked
-      // off, formed here (not hoisted out of the tile loop, where it would take a register)
-      int loff;
-      asm volatile("v_and_b32 %0, 0x3ff, %1" : "=v"(loff) : "v"(lane * 32));
-      const float4 v = rld4(lres, loff, hb * HPB * 4);
+      // row lr's normalisers at lr * 32 bytes: the x offset with the lane half masked off
+      const float4 v = rld4(lres, l32 & 0x3ff, hb * HPB * 4);
       ln[0] = v.x; ln[1] = v.y; ln[2] = v.z; ln[3] = v.w;
     } else {
-      const float2 v = rld2(lres, lr * (NB * HPB * 4) + hb * HPB * 4);
+      static_assert(NB * HPB * 4 == 16, "row lr's two normalisers of each head block at lr * 16 bytes");
+      const float2 v = rld2(lres, ((l32 & 0x3ff) >> 1) + hb * HPB * 4);
       ln[0] = v.x; ln[1] = v.y;
     }
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) {
-      xn[ib][0] = rld8(xres, lane * 32, ib * 64 * 16 * 2);
-      xn[ib][1] = rld8(xres, lane * 32, ib * 64 * 16 * 2 + 16);
+      xn[ib][0] = rld8(xres, l32, ib * 64 * 16 * 2);
+      xn[ib][1] = rld8(xres, l32, ib * 64 * 16 * 2 + 16);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) gn[ib][q] = rld4(gres, lane * 64, ib * 64 * 64 + 16 * q);
+      for (int q = 0; q < 4; ++q) gn[ib][q] = rld4(gres, 2 * l32, ib * 64 * 64 + 16 * q);
     }
   };
   fetch(blockIdx.x);
 
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    // rh opaque to the loop: the unit offsets rh ^ c are formed where used, not kept in registers
+    asm volatile("" : "+v"(rh));
     // ================= block phase: head block hb of block gb
-    const int64_t gb = 4 * tile + bw;
+    const int64_t gb = (int64_t)BPT * tile + bw;
     const bool valid = gb < nblk;
     __bf16* S = stg + bw * NSTAGE * MAT;
     // the block's x and g as BF16 operands (values tile_idx(8 s + t, h))
@@ -208,8 +223,8 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
     // the wave of head block 0 stages x, the other g
 #pragma unroll
     for (int ib = 0; ib < NB; ++ib) {
-      if (hb == 0) stage_r(S + SX * MAT, ib, xo[ib][0], xo[ib][1], lr, h);
-      else stage_r(S + SG * MAT, ib, go[ib][0], go[ib][1], lr, h);
+      if (hb == 0) stage_r(S + SX * MAT, ib, xo[ib][0], xo[ib][1], rh);
+      else stage_r(S + SG * MAT, ib, go[ib][0], go[ib][1], rh);
     }
 
     // projections of the 32 attention features of head block hb, row-major (*R: lane -> row,
@@ -250,8 +265,8 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       }
       // feature-major tiles through LDS: this wave's feature half of the dQ and dK staging
       // slots is free until it stages dQ and dK there after the head loop
-      stage_r(S + SQ * MAT, hb, rop(QRp, 0), rop(QRp, 1), lr, h);
-      stage_r(S + SK * MAT, hb, rop(KRp, 0), rop(KRp, 1), lr, h);
+      stage_r(S + SQ * MAT, hb, rop(QRp, 0), rop(QRp, 1), rh);
+      stage_r(S + SK * MAT, hb, rop(KRp, 0), rop(KRp, 1), rh);
 #pragma unroll
       for (int s = 0; s < ST; ++s) { QFb[s] = tr_op(S + SQ * MAT, thb + 1024 * s); KFb[s] = tr_op(S + SK * MAT, thb + 1024 * s); }
     }
@@ -274,8 +289,8 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
         VRp[j] = PBF16::pack_head<DH>(VR, j);
         ORp[j] = PBF16::pack_head<DH>(OR, j);
       }
-      stage_r(S + SV * MAT, hb, rop(VRp, 0), rop(VRp, 1), lr, h);
-      stage_r(S + SO * MAT, hb, rop(ORp, 0), rop(ORp, 1), lr, h);
+      stage_r(S + SV * MAT, hb, rop(VRp, 0), rop(VRp, 1), rh);
+      stage_r(S + SO * MAT, hb, rop(ORp, 0), rop(ORp, 1), rh);
 #pragma unroll
       for (int s = 0; s < ST; ++s) { VFb[s] = tr_op(S + SV * MAT, thb + 1024 * s); OFb[s] = tr_op(S + SO * MAT, thb + 1024 * s); }
     }
@@ -334,8 +349,8 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       // this wave's half of the dQ and dK staging slots (free until the staging after the head loop;
       // the previous head's reads of them are ordered before these writes), read back transposed
       // after the query-major products below are issued
-      stage_r(S + SQ * MAT, hb, Pq[0], Pq[1], lr, h);
-      stage_r(S + SK * MAT, hb, Sq[0], Sq[1], lr, h);
+      stage_r(S + SQ * MAT, hb, Pq[0], Pq[1], rh);
+      stage_r(S + SK * MAT, hb, Sq[0], Sq[1], rh);
       // two products at a time (four fresh accumulators at once would not fit in the registers)
       {
         f32x16 to = {}, tq = {};
@@ -377,20 +392,20 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       dk[s] = __builtin_bit_cast(bf16x8, kw[s]);
       dv[s] = __builtin_bit_cast(bf16x8, vw[s]);
     }
-    stage_r(S + SQ * MAT, hb, dq[0], dq[1], lr, h);
-    stage_r(S + SK * MAT, hb, dk[0], dk[1], lr, h);
-    stage_r(S + SV * MAT, hb, dv[0], dv[1], lr, h);
-    stage_r(S + SO * MAT, hb, __builtin_bit_cast(bf16x8, ow[0]), __builtin_bit_cast(bf16x8, ow[1]), lr, h);
+    stage_r(S + SQ * MAT, hb, dq[0], dq[1], rh);
+    stage_r(S + SK * MAT, hb, dk[0], dk[1], rh);
+    stage_r(S + SV * MAT, hb, dv[0], dv[1], rh);
+    stage_r(S + SO * MAT, hb, __builtin_bit_cast(bf16x8, ow[0]), __builtin_bit_cast(bf16x8, ow[1]), rh);
     // dx = g + dQ Wq^T + dK Wk^T + dV Wv^T, output feature block hb from this wave: after the
     // barrier it reads the other head block's dQ, dK, dV from the staging (the 16-byte operands
     // that wave staged) and sums (g + terms of attention block 0) + terms of attention block 1.
     // g is loaded before the barrier, where the wave may wait for the other waves.
     auto dx_terms = [&](int ib, const bf16x8 (&q)[ST], const bf16x8 (&k)[ST], const bf16x8 (&v)[ST]) {
       f32x16 acc = {};
-      const int voff = (ib * ST * 64 + lane) * 16;  // fragment ((hb NB + ib) ST + s) of each matrix
+      const int voff = lane * 16;  // fragment ((hb NB + ib) ST + s) of each matrix, ib in the scalar offset
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
-        const int so = (hb * NB * ST + s) * 64 * 16;
+        const int so = ((hb * NB + ib) * ST + s) * 64 * 16;
         acc = mfma16(rld8(WT, voff, so), q[s], acc);
         acc = mfma16(rld8(WT, voff, so + D * D * 2), k[s], acc);
         acc = mfma16(rld8(WT, voff, so + 2 * D * D * 2), v[s], acc);
@@ -411,7 +426,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
       bf16x8 oq[ST], ok[ST], ov[ST];  // the other head block's operands, as it staged them
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
-        const int e = lr * 64 + rsw(4 * (hb ^ 1) + 2 * s + h, lr) * 8;
+        const int e = rh ^ (32 * (hb ^ 1) + 16 * s);
         oq[s] = ld8(S + SQ * MAT + e);
         ok[s] = ld8(S + SK * MAT + e);
         ov[s] = ld8(S + SV * MAT + e);
@@ -441,31 +456,36 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
 
     // ================= gradient phase: wave w adds the tile's rows into its weight gradient rows
     {
-      const int am = (bw < 3) ? SX : SO;       // A operand: x (for Wq, Wk, Wv) or O (for W_O)
-      const int bm = (bw < 3) ? SQ + bw : SG;  // B operand: dQ, dK, dV or g
+      const int am = (w < 3) ? SX : SO;      // A operand: x (for Wq, Wk, Wv) or O (for W_O)
+      const int bm = (w < 3) ? SQ + w : SG;  // B operand: dQ, dK, dV or g
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
+      for (int b = 0; b < BPT; ++b) {
         const __bf16* A = stg + (b * NSTAGE + am) * MAT;
         const __bf16* B = stg + (b * NSTAGE + bm) * MAT;
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
-          const bf16x8 av = tr_op(A, thb + 1024 * s);
-          bf16x8 bv[NB];
+          bf16x8 av[NB], bv[NB];
+#pragma unroll
+          for (int k = 0; k < NB; ++k) av[k] = tr_op(A, tb[k] + 1024 * s);
 #pragma unroll
           for (int j = 0; j < NB; ++j) bv[j] = tr_op(B, tb[j] + 1024 * s);
 #pragma unroll
-          for (int j = 0; j < NB; ++j) dW[j] = mfma16(av, bv[j], dW[j]);
+          for (int k = 0; k < NB; ++k)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) dW[k][j] = mfma16(av[k], bv[j], dW[k][j]);
         }
       }
     }
     barrier_lds();  // staging read before the next tile overwrites it
   }
 
-  float* part = a.partial + (int64_t)blockIdx.x * 4 * D * D + (int64_t)bw * D * D;
+  float* part = a.partial + (int64_t)blockIdx.x * 4 * D * D + (int64_t)w * D * D;
 #pragma unroll
-  for (int j = 0; j < NB; ++j)
+  for (int k = 0; k < NB; ++k)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) part[(32 * hb + tile_idx(r, h)) * D + 32 * j + lr] = dW[j][r];
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) part[(32 * k + tile_idx(r, h)) * D + 32 * j + lr] = dW[k][j][r];
 }
 
 // Chains of 32 < n <= 64 sites: one configuration-pass spans two blocks (rows 0-31, 32-63;
@@ -475,7 +495,7 @@ __global__ void __launch_bounds__(512) k_bwd_attn_bf16(BwdArgs a) {
 // 2 x 2 (query block x key block), P comes from the forward's normalisers, dK and dV of a
 // key block sum over both query blocks.  Staging, the transposes through the transposing
 // LDS read, dx by output feature block and the per-wave weight gradients (wave w owns all
-// of Wq, Wk, Wv, W_O for w = 0..3) are those of the kernel above with 4 waves; the products
+// of Wq, Wk, Wv, W_O for w = 0..3) are those of the kernel above; the products
 // keep feature-major operands masked per head (fresh accumulators per head would not fit
 // next to the 2 x 2 tiles).  Padding rows add nothing: their keys have P = 0 and their
 // incoming gradient is 0 (it is formed from the seeds of valid rows only).
@@ -507,6 +527,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
   // transposing-read offsets, as in the kernel above
   const int tb[2] = {tr_off(4 * h + ((lane & 15) >> 2), 0, lane), tr_off(4 * h + ((lane & 15) >> 2), 1, lane)};
   const int thb = hb ? tb[1] : tb[0];
+  int rh = stage_rh(lr, h);
   // valid keys of the second key block: rows 32 + tile_idx(r, h) < n (the first block is all valid)
   uint32_t ok1 = 0;
 #pragma unroll
@@ -544,6 +565,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
   fetch(blockIdx.x);
 
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    asm volatile("" : "+v"(rh));  // the unit offsets rh ^ c are formed where used
     // ================= block phase: head block hb of configuration-pass cp (blocks 2 cp, 2 cp + 1)
     bf16x8 xo[2][NB][ST], go[2][NB][ST];
     float lse[2][HPB];
@@ -570,8 +592,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
       __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
 #pragma unroll
       for (int ib = 0; ib < NB; ++ib) {
-        if (hb == 0) stage_r(S + SX * MAT, ib, xo[rb][ib][0], xo[rb][ib][1], lr, h);
-        else stage_r(S + SG * MAT, ib, go[rb][ib][0], go[rb][ib][1], lr, h);
+        if (hb == 0) stage_r(S + SX * MAT, ib, xo[rb][ib][0], xo[rb][ib][1], rh);
+        else stage_r(S + SG * MAT, ib, go[rb][ib][0], go[rb][ib][1], rh);
       }
     }
     // projections of head block hb for both blocks (see the kernel above: the feature-major
@@ -609,8 +631,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           KRp[rb][j] = PBF16::pack_head<DH>(KR, j);
         }
         __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
-        stage_r(S + SQ * MAT, hb, rop(QRp[rb], 0), rop(QRp[rb], 1), lr, h);
-        stage_r(S + SK * MAT, hb, rop(KRp[rb], 0), rop(KRp[rb], 1), lr, h);
+        stage_r(S + SQ * MAT, hb, rop(QRp[rb], 0), rop(QRp[rb], 1), rh);
+        stage_r(S + SK * MAT, hb, rop(KRp[rb], 0), rop(KRp[rb], 1), rh);
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
           QFb[rb][s] = tr_op(S + SQ * MAT, thb + 1024 * s);
@@ -637,8 +659,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           ORp[rb][j] = PBF16::pack_head<DH>(OR, j);
         }
         __bf16* S = stg + (2 * cp + rb) * NSTAGE * MAT;
-        stage_r(S + SV * MAT, hb, rop(VRp[rb], 0), rop(VRp[rb], 1), lr, h);
-        stage_r(S + SO * MAT, hb, rop(ORp[rb], 0), rop(ORp[rb], 1), lr, h);
+        stage_r(S + SV * MAT, hb, rop(VRp[rb], 0), rop(VRp[rb], 1), rh);
+        stage_r(S + SO * MAT, hb, rop(ORp[rb], 0), rop(ORp[rb], 1), rh);
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
           VFb[rb][s] = tr_op(S + SV * MAT, thb + 1024 * s);
@@ -689,8 +711,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           bf16x8 Pq[ST], Sq[ST];
 #pragma unroll
           for (int s = 0; s < ST; ++s) { Pq[s] = cvt8(sq[kb], s); Sq[s] = cvt8(dpq[kb], s); }
-          stage_r(PS, hb, Pq[0], Pq[1], lr, h);
-          stage_r(DS, hb, Sq[0], Sq[1], lr, h);
+          stage_r(PS, hb, Pq[0], Pq[1], rh);
+          stage_r(DS, hb, Sq[0], Sq[1], rh);
 #pragma unroll
           for (int s = 0; s < ST; ++s) {
             AOR[qb] = mfma16(mine ? VFb[kb][s] : z, Pq[s], AOR[qb]);  // O[q][f]  += P[q][k] V[k][f]
@@ -714,19 +736,19 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
       for (int r = 0; r < 16; ++r) { dKR[rb][r] *= isc; dVR[rb][r] *= sdh; }
 #pragma unroll
       for (int s = 0; s < ST; ++s) { dq[rb][s] = cvt8(dQR[rb], s); dk[rb][s] = cvt8(dKR[rb], s); dv[rb][s] = cvt8(dVR[rb], s); }
-      stage_r(S + SQ * MAT, hb, dq[rb][0], dq[rb][1], lr, h);
-      stage_r(S + SK * MAT, hb, dk[rb][0], dk[rb][1], lr, h);
-      stage_r(S + SV * MAT, hb, dv[rb][0], dv[rb][1], lr, h);
-      stage_r(S + SO * MAT, hb, cvt8(AOR[rb], 0), cvt8(AOR[rb], 1), lr, h);
+      stage_r(S + SQ * MAT, hb, dq[rb][0], dq[rb][1], rh);
+      stage_r(S + SK * MAT, hb, dk[rb][0], dk[rb][1], rh);
+      stage_r(S + SV * MAT, hb, dv[rb][0], dv[rb][1], rh);
+      stage_r(S + SO * MAT, hb, cvt8(AOR[rb], 0), cvt8(AOR[rb], 1), rh);
     }
     // dx (as in the kernel above): output feature block hb from this wave, for both of its row
     // blocks; the other head block's dQ, dK, dV are read back from the staging after the barrier
     auto dx_terms = [&](int ib, const bf16x8 (&q)[ST], const bf16x8 (&k)[ST], const bf16x8 (&v)[ST]) {
       f32x16 acc = {};
-      const int voff = (ib * ST * 64 + lane) * 16;
+      const int voff = lane * 16;
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
-        const int so = (hb * NB * ST + s) * 64 * 16;
+        const int so = ((hb * NB + ib) * ST + s) * 64 * 16;
         acc = mfma16(rld8(WT, voff, so), q[s], acc);
         acc = mfma16(rld8(WT, voff, so + D * D * 2), k[s], acc);
         acc = mfma16(rld8(WT, voff, so + 2 * D * D * 2), v[s], acc);
@@ -748,7 +770,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
       bf16x8 oq[ST], ok[ST], ov[ST];  // the other head block's operands, as it staged them
 #pragma unroll
       for (int s = 0; s < ST; ++s) {
-        const int e = lr * 64 + rsw(4 * (hb ^ 1) + 2 * s + h, lr) * 8;
+        const int e = rh ^ (32 * (hb ^ 1) + 16 * s);
         oq[s] = ld8(S + SQ * MAT + e);
         ok[s] = ld8(S + SK * MAT + e);
         ov[s] = ld8(S + SV * MAT + e);
@@ -810,20 +832,22 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
       for (int r = 0; r < 16; ++r) part[(32 * i + tile_idx(r, h)) * D + 32 * j + lr] = dW[i][j][r];
 }
 
-size_t bwd_attn_bf16_lds() {
-  return (size_t)(4 * 64 * 64 + 4 * NSTAGE * MAT) * sizeof(__bf16);
+size_t bwd_attn_bf16_lds(int bpt) {
+  return (size_t)(4 * 64 * 64 + bpt * NSTAGE * MAT) * sizeof(__bf16);
 }
 
 bool bwd_attn_bf16_supported(int d, int D, int DH, bool span) { return d == 64 && D == 64 && (DH == 8 || DH == 16); }
 
+int bwd_attn_bf16_parts(int blocks, bool span) { return span ? blocks : 2 * blocks; }
+
 int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t st) {
-  const size_t lds = bwd_attn_bf16_lds();
+  const size_t lds = bwd_attn_bf16_lds(4);
   // written for distinct input and output gradient buffers
   TDO_CHECK(a.g_in != a.g_out, TDO_EINVAL, "BF16 attention backward cannot run in place");
   TDO_CHECK(a.lse != nullptr, TDO_EINVAL, "BF16 attention backward needs the forward's softmax normalisers");
   auto go = [&](auto kern) -> int32_t {
     TDO_TRY(allow_full_lds((const void*)kern));
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(512), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3(2 * blocks), dim3(256), bwd_attn_bf16_lds(ATTN_BPT), st, a);
     TDO_HIP(hipGetLastError());
     return TDO_OK;
   };

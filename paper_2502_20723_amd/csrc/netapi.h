@@ -80,6 +80,8 @@ int32_t launch_bwd_mlp_bf16(const BwdArgs& a, int blocks, hipStream_t st);
 // Attention backward with BF16 operands and per-wave register gradients (width 64, n <= 32).
 bool bwd_attn_bf16_supported(int d, int D, int DH, bool span);
 int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t st);
+// weight-gradient partial slots [4 D^2] that launch_bwd_attn_bf16 writes for `blocks` (one per CU)
+int bwd_attn_bf16_parts(int blocks, bool span);
 int32_t launch_bwd_mlp(const BwdArgs& a, bool bf16, int D, int blocks, hipStream_t st);
 int32_t launch_bwd_attn(const BwdArgs& a, bool bf16, int D, int DH, int blocks, hipStream_t st);
 // part: FP64 scratch of HEAD_BLOCKS * (2 d_real + 2) values (one slot per workgroup).

@@ -177,14 +177,17 @@ static int32_t run_backward(const NetPlan& np, const NetWeights& w, const BwdBuf
     a.g_in = bb.gb;
     a.seeds = nullptr;
     a.g_out = bb.ga;
+    int attn_parts = bb.nparts;
     {
       ProfScope ps(np.prof, "bwd_attn", st);
-      if (np.bf16 && bwd_attn_bf16_supported(pp.d, D, np.DH, np.span))
+      if (np.bf16 && bwd_attn_bf16_supported(pp.d, D, np.DH, np.span)) {
         TDO_TRY(launch_bwd_attn_bf16(a, np.DH, bb.nparts, st));
-      else
+        attn_parts = bwd_attn_bf16_parts(bb.nparts, np.span);
+      } else {
         TDO_TRY(launch_bwd_attn(a, np.bf16, D, np.DH, bb.nparts, st));
+      }
     }
-    TDO_TRY(launch_reduce_partials(bb.partial, bb.nparts, alen, bb.attn_acc, st));
+    TDO_TRY(launch_reduce_partials(bb.partial, attn_parts, alen, bb.attn_acc, st));
     TDO_TRY(launch_scatter_layer(bb.mlp_acc, bb.attn_acc, pp.d, D, M, 1.0, gt + pp.off_layer0 + l * pp.layer_stride, st));
   }
   // the head kernel's workgroup slots reuse the partial buffer (free here; sized for them in plan_train)
@@ -221,10 +224,10 @@ int32_t plan_train_at(const Context& c, const NetPlan& np, int64_t B, int nslots
   t->mlp_acc = ar.take<double>(mlen);
   t->attn_acc = ar.take<double>(4LL * np.D * np.D);
   t->dT_acc = ar.take<double>(64LL * np.D);
-  // per CU: the feed-forward or attention weight partials, or 8 wave partials of the table gradient;
-  // in all, at least the FP64 per-code slots of the embedding chain rule and the head kernel's
-  // workgroup slots
-  const int64_t maxlen = std::max<int64_t>(std::max<int64_t>(std::max<int64_t>(mlen, 4LL * np.D * np.D), 8 * 64LL * np.D),
+  // per CU: the feed-forward weight partials, the attention weight partials of up to two workgroups,
+  // or 8 wave partials of the table gradient; in all, at least the FP64 per-code slots of the
+  // embedding chain rule and the head kernel's workgroup slots
+  const int64_t maxlen = std::max<int64_t>(std::max<int64_t>(std::max<int64_t>(mlen, 2 * 4LL * np.D * np.D), 8 * 64LL * np.D),
                                            std::max<int64_t>(2 * 64 * (6LL * pp.d + 2LL * pp.d * pp.d),
                                                              2LL * HEAD_BLOCKS * (2 * pp.d + 2)) /
                                                    c.num_cus + 1);
