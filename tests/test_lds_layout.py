@@ -95,6 +95,19 @@ def test_attention_staging_conflict_free():
             assert conflict_free(ph, 8)
 
 
+def stage_rh(lr, h):
+    """The n <= 32 kernel's one-register form of a lane's unit offsets (see stage_rh there)."""
+    return lr * 64 | (rsw(h, lr) * 8)
+
+
+def test_attention_one_register_offsets():
+    # unit 4 fb + 2 s + h of row lr at rh ^ (32 fb + 16 s), for every unit the kernel writes or reads
+    # (the XOR touches bits 3..5 only, so it never reaches the row part)
+    for fb, s, lr, h in itertools.product(range(2), range(2), range(32), range(2)):
+        assert stage_r_addr(fb, s, lr, h) == stage_rh(lr, h) ^ (32 * fb + 16 * s)
+        assert (stage_rh(lr, h) ^ (32 * fb + 16 * s)) >> 6 == lr
+
+
 def test_attention_staging_halves_disjoint():
     # the two waves of a block stage feature blocks 0 and 1 of the same matrix: disjoint elements
     a = {stage_r_addr(0, s, lr, h) + t for s, lr, h, t in itertools.product(range(2), range(32), range(2), range(8))}
