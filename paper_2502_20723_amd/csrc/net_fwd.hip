@@ -92,12 +92,12 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
   extern __shared__ __align__(16) char smem[];
   const int M = MBC ? 32 * MBC : a.M, MB = M / 32;
   const int wtotal = 4 * D * D + 2 * D * M;
-  // LDS carve-up: [weights (BF16 only)] [b1 M] [b2 D] [table 64*D] [pool scratch: 64 float2 per wave]
+  // LDS carve-up: [weights (BF16 only)] [b1 M] [b2 D] [table 64*D] [head weights: 64 float2]
   elem_t* wl = reinterpret_cast<elem_t*>(smem);
   float* b1s = reinterpret_cast<float*>(smem + (WLDS ? (size_t)wtotal * sizeof(elem_t) : 0));
   float* b2s = b1s + M;
   float* tabs = b2s + D;
-  float2* pools = reinterpret_cast<float2*>(tabs + (a.first ? 64 * D : 0));
+  float2* hws = reinterpret_cast<float2*>(tabs + (a.first ? 64 * D : 0));  // last layer: (W_h[f][0], W_h[f][1]), 0 past d
 
   // ---- stage weights, biases and the embedding table
   const elem_t* wg = reinterpret_cast<const elem_t*>(a.wpack);
@@ -111,6 +111,9 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
   for (int i = threadIdx.x; i < D; i += blockDim.x) b2s[i] = a.b2[i];
   if (a.first)
     for (int i = threadIdx.x; i < 64 * D; i += blockDim.x) tabs[i] = a.table[i];
+  if (a.last)
+    for (int i = threadIdx.x; i < 64; i += blockDim.x)
+      hws[i] = i < a.d_real ? make_float2(a.head_w[2 * i], a.head_w[2 * i + 1]) : make_float2(0.f, 0.f);
   __syncthreads();
   const elem_t* W = WLDS ? wl : wg;
   const elem_t* Wq = W + 0 * D * D;
@@ -428,40 +431,44 @@ __global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
     }
     // ---- last layer: save x_L, mean pooling over sites, dense head to z (Eq. global-pool-final)
     if (a.save_last) save(a.save_last, x);
-    float2* pw = pools + wave * 64;
+    // per row: F = x_L W_h (features past d hold zero weights), summed over both lane halves
+    float f0[NBR], f1[NBR];
 #pragma unroll
     for (int rb = 0; rb < NBR; ++rb) {
-      float f0 = 0.f, f1 = 0.f;
+      float s0 = 0.f, s1 = 0.f;
 #pragma unroll
       for (int ob = 0; ob < NB; ++ob)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int f = 32 * ob + tile_idx(r, h);
-          if (f < a.d_real) {
-            f0 += x[rb][ob][r] * a.head_w[2 * f];
-            f1 += x[rb][ob][r] * a.head_w[2 * f + 1];
-          }
+          const float2 hw = hws[32 * ob + tile_idx(r, h)];
+          s0 += x[rb][ob][r] * hw.x;
+          s1 += x[rb][ob][r] * hw.y;
         }
-      f0 = xor32_sum(f0);
-      f1 = xor32_sum(f1);
-      if (h == 0) pw[rb * 32 + lr] = make_float2(f0, f1);
+      f0[rb] = xor32_sum(s0);
+      f1[rb] = xor32_sum(s1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int nslot = SPAN ? 1 : cpb;
-    if (lane < nslot) {
-      const int64_t e = e0 + lane;
+    // mean over the n sites of each configuration: a segmented inclusive scan over the 32 row
+    // lanes (segment = the configuration's rows; rows past the last configuration add nothing),
+    // a fixed order of additions; the last row of each segment then holds its sum
+    const int seg = SPAN ? 0 : lr / n, pos = SPAN ? lr : lr - seg * n;
+    float v0 = 0.f, v1 = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < NBR; ++rb)
+      if (rvalid[rb]) { v0 += f0[rb]; v1 += f1[rb]; }
+#pragma unroll
+    for (int dd = 1; dd < 32; dd <<= 1) {
+      const float t0 = __shfl_up(v0, dd, 32), t1 = __shfl_up(v1, dd, 32);
+      if (pos >= dd) { v0 += t0; v1 += t1; }
+    }
+    const int last = SPAN ? 31 : n - 1;  // in a spanning tile every lane's rows are one configuration
+    if (h == 0 && pos == last && (SPAN || seg < cpb)) {
+      const int64_t e = e0 + seg;
       if (e < E) {
-        float s0 = 0.f, s1 = 0.f;
-        const int base = SPAN ? 0 : lane * n;
-        for (int i = 0; i < n; ++i) { s0 += pw[base + i].x; s1 += pw[base + i].y; }
         const float inv = 1.0f / (float)n;
-        a.z[(e * 2 + pass) * 2 + 0] = s0 * inv + a.head_b[0];
-        a.z[(e * 2 + pass) * 2 + 1] = s1 * inv + a.head_b[1];
+        a.z[(e * 2 + pass) * 2 + 0] = v0 * inv + a.head_b[0];
+        a.z[(e * 2 + pass) * 2 + 1] = v1 * inv + a.head_b[1];
       }
     }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -487,7 +494,7 @@ __global__ void k_symmetrise(const int64_t* __restrict__ E_dev, int64_t E_host, 
 template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED, int NT>
 static int32_t launch_layer_nt(const FwdArgs& a, int num_cus, hipStream_t st) {
   const size_t wbytes = (P::KPL == 8) ? (size_t)(4 * D * D + 2 * D * a.M) * sizeof(typename P::elem_t) : 0;
-  const size_t lds = wbytes + (size_t)(a.M + D) * 4 + (a.first ? 64 * D * 4 : 0) + (NT / 64) * 64 * sizeof(float2);
+  const size_t lds = wbytes + (size_t)(a.M + D) * 4 + (a.first ? 64 * D * 4 : 0) + 64 * sizeof(float2);
   auto kern = k_fwd_layer<P, D, DH, SPAN, MBC, MASKED, NT>;
   TDO_TRY(allow_full_lds((const void*)kern));
   const int blocks = num_cus * a.blocks_per_cu;
