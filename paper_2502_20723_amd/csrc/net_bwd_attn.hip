@@ -505,7 +505,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
 // keep feature-major operands masked per head (fresh accumulators per head would not fit
 // next to the 2 x 2 tiles).  Padding rows add nothing: their keys have P = 0 and their
 // incoming gradient is 0 (it is formed from the seeds of valid rows only).
-template <int DH, bool MASKED>
+// PAD16 (n <= 48): rows 48..63 of a pass are padding, so every product whose contraction runs
+// over them adds exact zeros (keys: P = 0; queries: dS = 0 and dO = 0; rows of the weight
+// gradients: dQ, dK, dV, g = 0) and is skipped; the staged tiles are still written whole.
+template <int DH, bool MASKED, bool PAD16>
 __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
   constexpr int D = 64, NB = 2, ST = 2, HPB = 32 / DH;
   extern __shared__ __align__(16) char smem[];
@@ -704,6 +707,10 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
+            if (PAD16 && kb == 1 && r >= 8) {  // keys 48..63: P = 0, no exponential
+              sq[1][r] = 0.f;
+              continue;
+            }
             sq[kb][r] = __builtin_amdgcn_exp2f(sq[kb][r] - lse[qb][j]);  // P
             dl += sq[kb][r] * dpq[kb][r];
           }
@@ -711,7 +718,8 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
 #pragma unroll
-          for (int r = 0; r < 16; ++r) dpq[kb][r] = sq[kb][r] * (dpq[kb][r] - dl);  // dS (dP carries 1/sqrt(dh))
+          for (int r = 0; r < 16; ++r)  // dS (dP carries 1/sqrt(dh)); 0 at keys 48..63
+            dpq[kb][r] = (PAD16 && kb == 1 && r >= 8) ? 0.f : sq[kb][r] * (dpq[kb][r] - dl);
           bf16x8 Pq[ST], Sq[ST];
 #pragma unroll
           for (int s = 0; s < ST; ++s) { Pq[s] = cvt8(sq[kb], s); Sq[s] = cvt8(dpq[kb], s); }
@@ -719,11 +727,13 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
           stage_r(DS, hb, Sq[0], Sq[1], lr, h);
 #pragma unroll
           for (int s = 0; s < ST; ++s) {
+            if (PAD16 && kb == 1 && s == 1) continue;  // keys 48..63
             AOR[qb] = mfma16(mine ? VFb[kb][s] : z, Pq[s], AOR[qb]);  // O[q][f]  += P[q][k] V[k][f]
             dQR[qb] = mfma16(mine ? KFb[kb][s] : z, Sq[s], dQR[qb]);  // dQ[q][f] += dS[q][k] K[k][f]
           }
 #pragma unroll
           for (int s = 0; s < ST; ++s) {
+            if (PAD16 && qb == 1 && s == 1) continue;  // queries 48..63
             const bf16x8 Pk = tr_op(PS, thb + 1024 * s), Sk = tr_op(DS, thb + 1024 * s);
             dKR[kb] = mfma16(mine ? QFb[qb][s] : z, Sk, dKR[kb]);     // dK[k][f] += dS[q][k] Q[q][f]
             dVR[kb] = mfma16(mine ? OFb[qb][s] : z, Pk, dVR[kb]);     // dV[k][f] += P[q][k] dO[q][f]
@@ -811,6 +821,7 @@ __global__ void __launch_bounds__(256) k_bwd_attn_span_bf16(BwdArgs a) {
         const __bf16* B = stg + (b * NSTAGE + bm) * MAT;
 #pragma unroll
         for (int s = 0; s < ST; ++s) {
+          if (PAD16 && (b & 1) && s == 1) continue;  // rows 48..63 of the pass
           bf16x8 av[NB], bv[NB];
 #pragma unroll
           for (int i = 0; i < NB; ++i) {
@@ -862,9 +873,13 @@ int32_t launch_bwd_attn_bf16(const BwdArgs& a, int DH, int blocks, hipStream_t s
       TDO_HIP(hipGetLastError());
       return TDO_OK;
     };
-    const bool m = a.n < 64;
-    if (DH == 8) return m ? go4(k_bwd_attn_span_bf16<8, true>) : go4(k_bwd_attn_span_bf16<8, false>);
-    if (DH == 16) return m ? go4(k_bwd_attn_span_bf16<16, true>) : go4(k_bwd_attn_span_bf16<16, false>);
+    const bool m = a.n < 64, p16 = a.n <= 48;
+    if (DH == 8)
+      return p16 ? go4(k_bwd_attn_span_bf16<8, true, true>)
+                 : (m ? go4(k_bwd_attn_span_bf16<8, true, false>) : go4(k_bwd_attn_span_bf16<8, false, false>));
+    if (DH == 16)
+      return p16 ? go4(k_bwd_attn_span_bf16<16, true, true>)
+                 : (m ? go4(k_bwd_attn_span_bf16<16, true, false>) : go4(k_bwd_attn_span_bf16<16, false, false>));
     return set_error(TDO_EUNSUPPORTED, "BF16 attention backward: head width %d", DH);
   }
   if (DH == 8) return a.masked ? go(k_bwd_attn_bf16<8, true>) : go(k_bwd_attn_bf16<8, false>);
