@@ -91,6 +91,17 @@ def log_rho_bf16(theta, arch, cfg, n):
     return log_rho_emulated(theta, arch, cfg, n, "bf16")
 
 
+def log_rho_vjp_emulated(theta, arch, cfg, n, seed, prec):
+    """sum_b seed[b, 0] d Re log rho_b + seed[b, 1] d Im log rho_b, with the network
+    evaluated and differentiated at the emulated precision."""
+    dt, _ = _setup(prec)
+    th = torch.tensor(np.asarray(theta), dtype=dt, requires_grad=True)
+    lr = _log_rho(th, arch, np.asarray(cfg, dtype=np.uint64).reshape(-1, 2), n, prec)
+    s = torch.as_tensor(np.asarray(seed)).to(dt)
+    (g,) = torch.autograd.grad((s[:, 0] * lr.real + s[:, 1] * lr.imag).sum(), th)
+    return g.double().numpy()
+
+
 def loss_grad_emulated(theta, arch, model, cfg, weights, mode, prec):
     """(F, grad) of the cost at fixed samples (modes "A"/"B" as in oracle.vmc),
     with the network evaluated and differentiated at the emulated precision."""

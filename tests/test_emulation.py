@@ -51,3 +51,23 @@ def test_kink_margins_bounds_and_a_planted_kink():
     assert np.all(kink_margins(planted, arch, model, cfg) == 0)
     with pytest.raises(AssertionError):
         kink_free_configs(planted, arch, model, 2, 9)
+
+
+def test_vjp_emulation_fp32_is_the_oracle_and_bf16_is_not():
+    """The emulated VJP in FP32 agrees with the FP64 oracle's VJP to FP32 rounding, so the
+    emulation differentiates the same network with the same seed convention; in BF16 it
+    moves by the BF16 rounding (between 1e-4 and 0.2, pointing the oracle's way)."""
+    from tests.bf16_emulation import log_rho_vjp_emulated
+    wl = synth.workload("ising_n8")
+    arch = oa.Arch(**wl["arch"])
+    params = synth.params(wl["arch"], 3, "mid").astype(np.float64)
+    cfg = synth.configs(8, 5, 9)
+    seed = np.random.default_rng(4).standard_normal((5, 2))
+    ref = vmc.log_rho_vjp(params, arch, cfg, 8, seed)
+    r32 = log_rho_vjp_emulated(params, arch, cfg, 8, seed, "fp32")
+    r16 = log_rho_vjp_emulated(params, arch, cfg, 8, seed, "bf16")
+    e32 = np.linalg.norm(r32 - ref) / np.linalg.norm(ref)
+    e16 = np.linalg.norm(r16 - ref) / np.linalg.norm(ref)
+    assert e32 < 1e-5
+    assert 1e-4 < e16 < 0.2
+    assert np.dot(r16, ref) / (np.linalg.norm(r16) * np.linalg.norm(ref)) > 0.99

@@ -9,7 +9,7 @@ from oracle import lindblad as ol
 from oracle import vmc
 from paper_2502_20723_amd import synth
 from tests.bf16_emulation import (KINK_KAPPA, kink_free_configs, kink_margins, kink_sensitivity,
-                                  loss_grad_emulated)
+                                  log_rho_vjp_emulated, loss_grad_emulated)
 from tests.parity import rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -37,14 +37,18 @@ def cosine(a, b):
     return float(np.dot(a, b) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-300))
 
 
-def assert_grad(prec, got, params, arch, model, cfg, w, mode, g_ref):
-    """The gradient criteria above, with every figure printed."""
+def assert_grad(prec, got, params, arch, model, cfg, w, mode, g_ref, emulate=None):
+    """The gradient criteria above, with every figure printed.  emulate() gives the
+    gradient at the emulated precision (default: the loss gradient of these inputs)."""
     gerr = rel_l2(got, g_ref)
     if prec == "fp32" or gerr < GTOL[prec]:
         assert gerr < GTOL[prec], f"{prec} gradient rel L2 {gerr:.3e} >= {GTOL[prec]}"
         return
-    A, M = oa.Arch(**arch), ol.Model(**model)
-    _, ge = loss_grad_emulated(params, A, M, cfg, w, mode, prec)
+    if emulate is None:
+        A, M = oa.Arch(**arch), ol.Model(**model)
+        _, ge = loss_grad_emulated(params, A, M, cfg, w, mode, prec)
+    else:
+        ge = emulate()
     emu, dist, cos = rel_l2(ge, g_ref), rel_l2(got, ge), cosine(got, g_ref)
     print(f"  bf16: emulation err {emu:.3e}, GPU distance to the emulation {dist:.3e}, cosine {cos:.4f}")
     if 2.0 * emu < BF16_CAP:
@@ -60,8 +64,11 @@ def cuda(x):
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("name,n,B", [("ising_n4", 4, 64), ("ising_n8", 8, 100), ("ising_n8", 5, 37),
                                       ("xyz_n16", 16, 50), ("ising_n32", 32, 40), ("ising_n32", 27, 23),
-                                      ("batched_uneven", 40, 12), ("batched_uneven", 64, 5)])
+                                      ("batched_uneven", 33, 9), ("batched_uneven", 40, 12), ("batched_uneven", 48, 7),
+                                      ("batched_uneven", 49, 6), ("batched_uneven", 64, 5)])
 def test_log_rho_vjp(gpu, name, n, B, prec):
+    # n = 33..64 span two row blocks; n <= 48 runs the attention backward's variant that skips
+    # the products over rows 48..63 (n = 48 keeps all of rows 32..47), n = 49 the one that does not
     arch = ARCH[name]
     params = synth.params(arch, 31 + n, "mid")
     cfg = synth.configs(n, B, 37 + n)
@@ -71,7 +78,10 @@ def test_log_rho_vjp(gpu, name, n, B, prec):
     ref = vmc.log_rho_vjp(params.astype(np.float64), oa.Arch(**arch), cfg, n, seed.astype(np.float64))
     err = rel_l2(got, ref)
     print(f"vjp {name} n={n} B={B} {prec}: rel L2 {err:.3e}")
-    assert err < GTOL[prec]
+    # the criteria of the loss gradient (above), against the emulated VJP of the same inputs
+    assert_grad(prec, got, params, arch, None, cfg, None, None, ref,
+                emulate=lambda: log_rho_vjp_emulated(params.astype(np.float64), oa.Arch(**arch), cfg, n,
+                                                     seed.astype(np.float64), prec))
 
 
 def model_of(name, n=None):
