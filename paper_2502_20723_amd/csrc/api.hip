@@ -199,7 +199,7 @@ int32_t net_plan(const Context* c, const tdo_arch_t* arch, int n, bool bf16, Net
   np->num_cus = c->num_cus;
   np->prof = const_cast<Profiler*>(&c->prof);
   np->fwd_wg_per_cu = 1;
-  np->fwd_waves = (bf16 && !np->span) ? 8 : 4;
+  np->fwd_waves = bf16 ? 8 : 4;
   np->mlp_waves = (bf16 && np->pp.M == 256) ? 8 : 4;
   const uint64_t key = tune_key(*np);
   for (const TuneEntry& e : c->tune)

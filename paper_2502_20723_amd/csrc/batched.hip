@@ -46,7 +46,7 @@ float time_twice(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F&& fn) {
   return ms;
 }
 
-// Tile shapes of one problem's (chain length, precision, width, head width, depth, MLP width):
+//  1. the forward layer kernel: workgroups of 8 waves (two per SIMD, BF16 only) or
 //  1. the forward layer kernel: workgroups of 8 waves (two per SIMD, BF16 with n <= 32 only) or
 //     4 waves, and 1 or 2 workgroups per CU, timed on the full forward over the problem's
 //     samples;
@@ -82,7 +82,7 @@ int32_t tune_problem(Context& c, NetPlan& np, const ModelDev& m, const TrainWs& 
   {
     NetWeights w = weights_at(c.ws, woff);
     rc = pack_weights(np, params, &w, st);
-    const bool two_shapes = np.bf16 && !np.span;
+    const bool two_shapes = np.bf16;
     const int waves_c[2] = {8, 4}, wg_c[2] = {1, 2};
     float best = -1.f;
     int bw = np.fwd_waves, bg = np.fwd_wg_per_cu;

@@ -70,16 +70,19 @@ __global__ void k_embed_table(const float* __restrict__ params, int d, int D, fl
 }
 
 // Workgroup size NT: BF16 weights staged in LDS are shared by 8 waves (two per SIMD,
-// so that one wave's latencies overlap the other's work) when a wave's registers
-// fit in half a SIMD (one 32-row block per wave), or by 4 waves (one per SIMD, with
-// twice the registers); the choice is autotuned per shape.  Otherwise 4 waves.
+// so that one wave's latencies overlap the other's work) or by 4 waves (one per SIMD,
+// with twice the registers); the choice is autotuned per shape.  Otherwise 4 waves.
+// A wave of a spanning pass (two row blocks) needs more than half a SIMD's registers:
+// with 8 waves it is held to 256 and spills a few values (24 at head width 16 with
+// masking), which measured faster than one wave per SIMD.
 
 // MBC: the feed-forward width in 32-column chunks when fixed at compile time (0: a.M / 32), so
 // that the chunk loop unrolls and one chunk's LDS reads overlap the previous chunk's products.
 // MASKED: some (query, key) pairs of a tile are invalid (several configurations per block, or
 // padding rows); a compile-time choice, so that the unmasked kernel holds no mask registers.
 template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED, int NT>
-__global__ void __launch_bounds__(NT) k_fwd_layer(FwdArgs a) {
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu((SPAN && NT == 512) ? 2 : 1, (SPAN && NT == 512) ? 2 : 8))) k_fwd_layer(FwdArgs a) {
   constexpr int NB = D / 32;            // feature blocks
   constexpr int NBR = SPAN ? 2 : 1;     // row blocks per wave
   constexpr int HPB = 32 / DH;          // heads per 32-feature block
@@ -505,7 +508,7 @@ static int32_t launch_layer_nt(const FwdArgs& a, int num_cus, hipStream_t st) {
 
 template <class P, int D, int DH, bool SPAN, int MBC, bool MASKED>
 static int32_t launch_layer_m(const FwdArgs& a, int num_cus, hipStream_t st) {
-  if constexpr (P::KPL == 8 && !SPAN)
+  if constexpr (P::KPL == 8)
     if (a.waves == 8) return launch_layer_nt<P, D, DH, SPAN, MBC, MASKED, 512>(a, num_cus, st);
   return launch_layer_nt<P, D, DH, SPAN, MBC, MASKED, 256>(a, num_cus, st);
 }
