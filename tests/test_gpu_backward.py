@@ -65,10 +65,12 @@ def cuda(x):
 @pytest.mark.parametrize("name,n,B", [("ising_n4", 4, 64), ("ising_n8", 8, 100), ("ising_n8", 5, 37),
                                       ("xyz_n16", 16, 50), ("ising_n32", 32, 40), ("ising_n32", 27, 23),
                                       ("batched_uneven", 33, 9), ("batched_uneven", 40, 12), ("batched_uneven", 48, 7),
-                                      ("batched_uneven", 49, 6), ("batched_uneven", 64, 5)])
+                                      ("batched_uneven", 49, 6), ("batched_uneven", 64, 5), ("ising_n32", 40, 10),
+                                      ("ising_n32", 56, 6)])
 def test_log_rho_vjp(gpu, name, n, B, prec):
     # n = 33..64 span two row blocks; n <= 48 runs the attention backward's variant that skips
-    # the products over rows 48..63 (n = 48 keeps all of rows 32..47), n = 49 the one that does not
+    # the products over rows 48..63 (n = 48 keeps all of rows 32..47), n = 49 the one that does
+    # not; the benchmark network (8-wide heads) at n = 40 and 56 takes both with its head width
     arch = ARCH[name]
     params = synth.params(arch, 31 + n, "mid")
     cfg = synth.configs(n, B, 37 + n)

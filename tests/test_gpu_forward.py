@@ -25,6 +25,8 @@ CASES = [  # (arch name, n, B)
     ("ising_n4", 4, 256), ("ising_n4", 3, 37), ("ising_n8", 8, 1000), ("ising_n8", 5, 333),
     ("xyz_n16", 16, 600), ("xyz_n16", 7, 129), ("ising_n32", 32, 300), ("ising_n32", 29, 65),
     ("batched_uneven", 40, 200), ("batched_uneven", 33, 31), ("batched_uneven", 64, 20), ("batched_uneven", 24, 77),
+    # spanning passes at the other widths: the benchmark network (8-wide heads), width 32, width 16
+    ("ising_n32", 40, 40), ("ising_n8", 45, 50), ("ising_n4", 36, 40),
 ]
 
 
