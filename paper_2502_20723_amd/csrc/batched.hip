@@ -46,8 +46,8 @@ float time_twice(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F&& fn) {
   return ms;
 }
 
+// Tile shapes of one problem's (chain length, precision, width, head width, depth, MLP width):
 //  1. the forward layer kernel: workgroups of 8 waves (two per SIMD, BF16 only) or
-//  1. the forward layer kernel: workgroups of 8 waves (two per SIMD, BF16 with n <= 32 only) or
 //     4 waves, and 1 or 2 workgroups per CU, timed on the full forward over the problem's
 //     samples;
 //  2. the BF16 feed-forward backward at MLP width 256: 8 or 4 waves per workgroup, timed on the
